@@ -1,0 +1,195 @@
+#!/usr/bin/env python3
+"""Throughput of the D2Q37 thermal lattice Boltzmann step on one MI355X.
+
+Workload (default): the 2048x4096 Rayleigh-Taylor lattice in FP64 -- walls at
+T = 4/3 (bottom) and 2/3 (top), x periodic, gravity g_y = -1e-5, tau = 0.7,
+two layers of density/temperature ratio 2:1 whose interface is displaced by
+seeded uniform noise of amplitude 1e-3.  A step is one propagate + bc +
+collide pass over the whole lattice; the metric is MLUPS (million lattice
+site updates per second), inputs resident in HBM.
+
+Printed: one JSON line with the FP64 MLUPS as `value`, the FP32-shifted
+MLUPS and ratio, the adjoint/forward cost ratio, the roofline of the dominant
+kernel (timed with HIP events on the library's stream) and the CPU oracle's
+rate on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
+FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 vector
+FP32_PEAK_TFLOPS = 157.3
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def time_launches(fn, stream, reps):
+    """Average duration of fn() over reps launches, HIP events on `stream`."""
+    import torch
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for _ in range(reps):
+        fn()
+    end.record(stream)
+    end.synchronize()
+    return start.elapsed_time(end) / reps * 1e-3
+
+
+def run(args):
+    import numpy as np
+    import torch
+
+    from paper_1703_04594_amd import inputs
+    from paper_1703_04594_amd.lbm import Lattice
+
+    lx, ly = args.lx, args.ly
+    tau, g, tb, tt = 0.7, -1e-5, 4 / 3, 2 / 3
+    sites = lx * ly
+    dev = "cuda:0"
+    P = torch.tensor(inputs.rt_perturbation(lx, ly, 1), device=dev)
+    out = {}
+
+    def make(precision, step, adjoint=False):
+        lat = Lattice(lx, ly, tau, g, tb, tt, precision=precision, step=step, adjoint=adjoint, device=dev)
+        lat.init_rt(P)
+        return lat
+
+    def mlups(lat, steps, warmup):
+        lat.step(warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lat.step(steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        return sites * steps / dt / 1e6, dt
+
+    # ---- headline: FP64 step ------------------------------------------------
+    log(f"bench: FP64 {lx}x{ly}, fused step, warmup {args.warmup}, steps {args.steps}")
+    lat = make("fp64", "fused")
+    fp64_mlups, dt = mlups(lat, args.steps, args.warmup)
+    out["fp64"] = dict(mlups=fp64_mlups, seconds=dt)
+    s = lat.stream
+    t_fused = time_launches(lambda: lat.step(1), s, 20)
+    del lat
+    torch.cuda.empty_cache()
+
+    log("bench: FP64 split step and its kernels")
+    lat = make("fp64", "split")
+    split_mlups, _ = mlups(lat, max(20, args.steps // 10), 5)
+    t_prop = time_launches(lat.propagate, s, 20)
+    t_coll = time_launches(lat.collide, s, 20)
+    del lat
+    torch.cuda.empty_cache()
+
+    log("bench: FP32-shifted")
+    lat = make("fp32", "fused")
+    fp32_mlups, _ = mlups(lat, args.steps, args.warmup)
+    t_fused32 = time_launches(lambda: lat.step(1), s, 20)
+    del lat
+    torch.cuda.empty_cache()
+
+    log("bench: adjoint step (FP32 state, FP64 lambda)")
+    lat = make("fp32", "fused", adjoint=True)
+    lat.step(10)
+    st = lat.get_state()
+    lat.step(1)
+    dacc = torch.zeros((), dtype=torch.float64, device=dev)
+    lat.seed_temperature(torch.ones((lx, ly), dtype=torch.float64, device=dev))
+    t_adj = time_launches(lambda: lat.adjoint_step(st, dacc), s, 10)
+    t_fwd32 = time_launches(lambda: lat.step(1), s, 10)
+    del lat, st
+    torch.cuda.empty_cache()
+
+    bytes_fp64 = 2 * 37 * 8 * sites   # one read + one write of every population
+    bytes_fp32 = 2 * 37 * 4 * sites
+    achieved = bytes_fp64 / t_fused / 1e9
+    res = {
+        "metric": "MLUPS D2Q37 step FP64 vs FP32 (+%HBM/%FLOP peak); adjoint/forward cost ratio",
+        "value": round(fp64_mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(dt / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"D2Q37 Rayleigh-Taylor {lx}x{ly} FP64, walls, tau=0.7, g=-1e-5",
+                   "lx": lx, "ly": ly, "step": "fused gather+bc+collide"},
+        "fp32_shifted_mlups": round(fp32_mlups, 1),
+        "fp32_over_fp64": round(fp32_mlups / fp64_mlups, 3),
+        "fp64_split_mlups": round(split_mlups, 1),
+        "adjoint_over_forward_fp32": round(t_adj / t_fwd32, 3),
+        "kernel_ms": {"fused_fp64": round(t_fused * 1e3, 4), "fused_fp32": round(t_fused32 * 1e3, 4),
+                      "propagate_fp64": round(t_prop * 1e3, 4), "collide_fp64": round(t_coll * 1e3, 4),
+                      "adjoint_step_fp32": round(t_adj * 1e3, 4), "step_fp32": round(t_fwd32 * 1e3, 4)},
+        "hbm_frac": {"fused_fp64": round(bytes_fp64 / t_fused / 1e9 / HBM_PEAK_GBS, 3),
+                     "fused_fp32": round(bytes_fp32 / t_fused32 / 1e9 / HBM_PEAK_GBS, 3),
+                     "propagate_fp64": round(bytes_fp64 / t_prop / 1e9 / HBM_PEAK_GBS, 3),
+                     "collide_fp64": round(bytes_fp64 / t_coll / 1e9 / HBM_PEAK_GBS, 3)},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "k_step_fused<double,wrap,walls>", "bytes_per_site": 592},
+    }
+    return res
+
+
+def cpu_baseline(args, budget_s=15.0):
+    """The oracle (OpenMP build of the plain C source) on the host cores, on a
+    bounded number of steps of the same lattice."""
+    import numpy as np
+
+    import oracle
+    from paper_1703_04594_amd import inputs
+
+    lx, ly = args.lx, args.ly
+    P = inputs.rt_perturbation(lx, ly, 1)
+    y = np.arange(ly)[None, :]
+    T0 = 1.0 - np.tanh((y - (ly - 1) / 2 - P) / 2.0) / 3.0
+    L = oracle.RefLattice(lx, ly, 0.7, -1e-5, 4 / 3, 2 / 3, openmp=True)
+    L.init((8 / 9) / T0, 0.0, 0.0, T0)
+    t0 = time.perf_counter()
+    L.step(1)
+    t1 = time.perf_counter() - t0
+    n = max(1, int(budget_s / max(t1, 1e-3)))
+    log(f"bench: cpu oracle, {n} steps (1 step took {t1:.2f}s)")
+    t0 = time.perf_counter()
+    L.step(n)
+    dt = time.perf_counter() - t0
+    return {"value": round(lx * ly * n / dt / 1e6, 3), "unit": "MLUPS", "cores": oracle.threads(True),
+            "kind": "oracle", "sample": f"{n} FP64 steps of the {lx}x{ly} RT lattice after 1 untimed step"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--lx", type=int, default=2048)
+    ap.add_argument("--ly", type=int, default=4096)
+    ap.add_argument("--skip-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build runs on one GPU only; multi-GPU X-slab sharding is not implemented",
+              file=sys.stderr)
+        sys.exit(2)
+    res = run(args)
+    res["cpu_baseline"] = None if args.skip_cpu else cpu_baseline(args)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

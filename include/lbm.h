@@ -1,0 +1,201 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) D2Q37 thermal lattice Boltzmann
+ * library, liblbm.so.
+ *
+ * The method is the one of Calore, Gabbana, Schifano, Tripiccione,
+ * "Optimization of Lattice Boltzmann Simulations on Heterogeneous Computers"
+ * (arXiv:1703.04594), section 3: populations f_l on a 2-D lattice evolve by
+ * the BGK equation, eq. (1); density, velocity and temperature are the
+ * moments of eq. (2); one time step is the pull streaming of eq. (4)
+ * ("propagate"), the wall boundary condition ("bc") on the three lowest and
+ * three highest rows, and the collision ("collide"), run in that order
+ * (section 5, control flow of one time step).
+ *
+ * Model readings where the paper defers to its model references:
+ *  - 37 hops e_l with |e|^2 in {0,1,2,4,5,8,9,10} (every hop at most 3 sites),
+ *    canonical order by |e|^2 then angle in [0, 2 pi) -- lbm_velocity_table;
+ *  - xi_l = c e_l, weights and c from the 8th-order Gaussian moment equations;
+ *  - f^eq: 4th-order Hermite expansion of the Maxwellian in D = 2;
+ *  - gravity g = (0, g_y) by shifting the equilibrium: u* = u + tau g,
+ *    T* = T + tau (1 - tau) g_y^2 / 2;
+ *  - walls: after propagate, each slot of the 3 bottom (top) rows whose pull
+ *    source lies below (above) the lattice receives f^eq_l(1, 0, T_wall) times
+ *    the pre-propagate density of the fluid site mirroring that source across
+ *    the wall (row -1-k <-> row k; row LY+k <-> row LY-1-k); x is periodic.
+ *
+ * Conventions
+ *  - Every array pointer is a DEVICE pointer owned by the caller (for
+ *    instance the data_ptr() of a torch tensor on the same device), unless a
+ *    parameter says "host".  The library never allocates device memory: all
+ *    of its buffers live in the caller's workspace.
+ *  - Field arrays are [lx][ly], y fastest, FP64.
+ *  - "Canonical" population arrays are [37][lx][ly], y fastest, in the storage
+ *    precision: FP64 populations f_l for LBM_FP64; FP32 deviations
+ *    f_l - w_l for LBM_FP32_SHIFTED.
+ *  - "State" arrays hold one population buffer in the library's internal
+ *    padded layout (lbm_state_bytes bytes); they are opaque, for snapshots.
+ *  - All calls enqueue work on the stream given to lbm_create and return
+ *    without waiting.  Argument and state errors are reported at once; a
+ *    failed launch returns LBM_ERR_HIP; faults of running kernels surface at
+ *    lbm_sync or at a later call.  lbm_last_error gives the message.
+ *  - A context is used by one host thread at a time.  Two contexts may share
+ *    nothing but the device.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBM_NPOP 37
+
+typedef struct lbm_ctx lbm_ctx;
+
+typedef enum {
+    LBM_OK = 0,
+    LBM_ERR_INVALID = 1,  /* bad argument or parameter                      */
+    LBM_ERR_SIZE = 2,     /* workspace too small                            */
+    LBM_ERR_HIP = 3,      /* a HIP call or kernel launch failed             */
+    LBM_ERR_STATE = 4     /* call not allowed in the context's current state */
+} lbm_status;
+
+typedef enum { LBM_FP64 = 0, LBM_FP32_SHIFTED = 1 } lbm_precision;
+typedef enum { LBM_Y_WALLS = 0, LBM_Y_PERIODIC = 1 } lbm_ybc;
+/* How x-periodicity reaches propagate: wrap the source column index inside the
+ * kernel, or first copy 3-column halos (the in-GPU form of the paper's halo
+ * exchange between lattice regions, section 5). Results are identical. */
+typedef enum { LBM_X_WRAP = 0, LBM_X_HALO = 1 } lbm_xmode;
+/* lbm_step as three kernels (propagate, bc, collide) or as one fused
+ * gather-collide pass (eq. (4) evaluated per site). Results are identical up
+ * to rounding order (none: both evaluate the same expressions). */
+typedef enum { LBM_STEP_SPLIT = 0, LBM_STEP_FUSED = 1 } lbm_step_kind;
+
+typedef struct {
+    int32_t lx, ly;        /* lattice sites; lx >= 7, ly >= 7               */
+    int32_t precision;     /* lbm_precision                                  */
+    int32_t ybc;           /* lbm_ybc                                        */
+    int32_t xmode;         /* lbm_xmode                                      */
+    int32_t step_kind;     /* lbm_step_kind                                  */
+    int32_t adjoint;       /* nonzero: also reserve the adjoint buffers      */
+    int32_t reserved;      /* must be 0                                      */
+    double tau;            /* relaxation time, > 0.5                         */
+    double g_y;            /* gravity, lattice units per step (y component)  */
+    double t_bottom;       /* wall temperatures (ignored for LBM_Y_PERIODIC) */
+    double t_top;
+} lbm_params;
+
+/* Rayleigh-Taylor initial profile: T0(x,y) = t_mid - t_amp *
+ * tanh((y - y_mid - P(x,y)) / width), rho0 = p0 / T0, u0 = 0. */
+typedef struct {
+    double t_mid, t_amp, p0, width, y_mid;
+} lbm_rt_profile;
+
+/* ---- sizes and lifetime -------------------------------------------------- */
+
+/* Bytes of device workspace lbm_create needs; 0 if *p is invalid. */
+size_t lbm_workspace_bytes(const lbm_params* p);
+/* Bytes of one opaque state snapshot; 0 if *p is invalid. */
+size_t lbm_state_bytes(const lbm_params* p);
+
+/* Validates *p (lx, ly >= 7, tau > 0.5, known enums, reserved == 0) and binds
+ * a context to dev_workspace (>= lbm_workspace_bytes(p) bytes, 256-byte
+ * aligned, caller-owned, must outlive the context) and hip_stream (a
+ * hipStream_t, or NULL for the default stream).  Zeroes the workspace.  The
+ * context holds host-side metadata only. */
+lbm_status lbm_create(const lbm_params* p, void* dev_workspace, size_t bytes,
+                      void* hip_stream, lbm_ctx** out);
+/* Frees the host-side context; never touches the workspace. NULL is a no-op. */
+void lbm_destroy(lbm_ctx* ctx);
+/* Changes tau (> 0.5) for subsequent collide and adjoint calls. */
+lbm_status lbm_set_tau(lbm_ctx* ctx, double tau);
+
+/* ---- initial state ------------------------------------------------------- */
+
+/* f = f^eq(rho, (ux, uy), T) at every site (eq. (2)'s moments of the
+ * result are the given fields).  Fields: device FP64 [lx][ly]. */
+lbm_status lbm_init(lbm_ctx* ctx, const double* rho, const double* ux,
+                    const double* uy, const double* T);
+/* f = f^eq of the Rayleigh-Taylor profile *prof (host struct) displaced by
+ * the device FP64 field P [lx][ly]. */
+lbm_status lbm_init_rt(lbm_ctx* ctx, const double* P, const lbm_rt_profile* prof);
+
+/* ---- the time step (section 5 order: propagate, bc, collide) -------------- */
+
+/* Pull streaming, eq. (4): next_l(x, y) = cur_l(x - ex_l, y - ey_l) for every
+ * population and site, x periodic (y periodic for LBM_Y_PERIODIC).  Writes
+ * the other buffer, which becomes current; the old one is kept for lbm_bc. */
+lbm_status lbm_propagate(lbm_ctx* ctx);
+/* Wall rule (see above) on the current buffer, reading the buffer before the
+ * last propagate.  No-op for LBM_Y_PERIODIC.  LBM_ERR_STATE if no propagate
+ * has run since the state was set. */
+lbm_status lbm_bc(lbm_ctx* ctx);
+/* BGK collision, eq. (1) with dt = 1, in place on the current buffer:
+ * moments (eq. (2)), gravity shift, equilibrium, f <- f + (f^eq - f)/tau. */
+lbm_status lbm_collide(lbm_ctx* ctx);
+/* n >= 0 times (propagate, bc, collide), split or fused per step_kind. */
+lbm_status lbm_step(lbm_ctx* ctx, int64_t n);
+
+/* ---- read-out and snapshots ---------------------------------------------- */
+
+/* Moments of eq. (2) of the current state, computed in FP64: rho,
+ * u = sum xi f / rho, T = sum |xi - u|^2 f / (2 rho).  Device FP64 [lx][ly]. */
+lbm_status lbm_get_macros(lbm_ctx* ctx, double* rho, double* ux, double* uy, double* T);
+/* Canonical population copies (device, storage precision). set_pops clears
+ * the "previous buffer" so lbm_bc needs a propagate first. */
+lbm_status lbm_get_pops(lbm_ctx* ctx, void* dst);
+lbm_status lbm_set_pops(lbm_ctx* ctx, const void* src);
+/* Opaque padded-state snapshots, lbm_state_bytes each (device). */
+lbm_status lbm_get_state(lbm_ctx* ctx, void* dst);
+lbm_status lbm_set_state(lbm_ctx* ctx, const void* src);
+/* Lattice totals of the collision invariants, accumulated in FP64 with a
+ * fixed reduction order (bitwise reproducible): out4 = {sum rho, sum j_x,
+ * sum j_y, sum E}, E = sum_l |xi_l|^2 f_l.  dev_out4: device FP64 [4]. */
+lbm_status lbm_conservation(lbm_ctx* ctx, double* dev_out4);
+
+/* ---- adjoint (requires params.adjoint != 0) ------------------------------- */
+/* The adjoint state lambda = dL/df (FP64, one value per population and site)
+ * lives in the workspace.  A reverse sweep is: seed lambda_N, then for
+ * n = N-1 .. 0 call lbm_adjoint_step with the forward state f_n, then
+ * lbm_adjoint_init_rt for dL/dP. */
+
+/* lambda <- dL/df of L = 1/2 sum (T - T_target)^2 at the current state;
+ * *dev_loss (device FP64 scalar) <- L.  T_target: device FP64 [lx][ly]. */
+lbm_status lbm_loss_temperature(lbm_ctx* ctx, const double* T_target, double* dev_loss);
+/* lambda <- sum_{x,y} dT(x,y) dT(x,y)/df at the current state: the adjoint
+ * seed for an arbitrary upstream gradient dT of the temperature field. */
+lbm_status lbm_adjoint_seed_temperature(lbm_ctx* ctx, const double* dT);
+/* One reverse step: with f_n (a device state snapshot, lbm_state_bytes,
+ * as written by lbm_get_state after n forward steps) and lambda_{n+1} in the
+ * context, replaces lambda by lambda_n = (d step / d f_n)^T lambda_{n+1}
+ * (collide^T, bc^T and propagate^T) and adds lambda_{n+1} . d step/d tau to
+ * *dev_dtau_acc (device FP64 scalar).  Uses the context's population
+ * buffers as scratch: set the forward state again before stepping forward. */
+lbm_status lbm_adjoint_step(lbm_ctx* ctx, const void* f_n_state, double* dev_dtau_acc);
+/* dP <- dL/dP for the initial state of lbm_init_rt(P, prof), from lambda_0. */
+lbm_status lbm_adjoint_init_rt(lbm_ctx* ctx, const double* P,
+                               const lbm_rt_profile* prof, double* dP);
+/* Canonical FP64 [37][lx][ly] copies of lambda (device). */
+lbm_status lbm_adjoint_get_lambda(lbm_ctx* ctx, double* dst);
+lbm_status lbm_adjoint_set_lambda(lbm_ctx* ctx, const double* src);
+
+/* ---- misc ------------------------------------------------------------------ */
+
+/* Waits for the context's stream; LBM_ERR_HIP if queued work failed. */
+lbm_status lbm_sync(lbm_ctx* ctx);
+/* Message of the last error on this context ("" if none); NULL ctx: last
+ * error of lbm_create on this thread. */
+const char* lbm_last_error(const lbm_ctx* ctx);
+/* Canonical population order (host arrays of 37). */
+void lbm_velocity_table(int8_t ex[LBM_NPOP], int8_t ey[LBM_NPOP]);
+/* Weights w_l and the scale c (host). */
+void lbm_weights(double w[LBM_NPOP]);
+double lbm_scale_c(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_H */

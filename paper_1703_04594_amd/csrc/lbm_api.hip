@@ -1,0 +1,487 @@
+// lbm_api.hip -- host side of liblbm.so: the C ABI declared in include/lbm.h.
+//
+// The context keeps only host metadata; every byte of device memory the
+// library uses is carved out of the caller's workspace (see plan()).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "lbm.h"
+#include "lbm_adjoint.hpp"
+#include "lbm_kernels.hpp"
+
+using namespace lbm;
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+constexpr size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct Plan {
+    Geo geo;          // population buffers, storage precision
+    Geo lgeo;         // adjoint lambda buffers, FP64
+    size_t elem;      // bytes per stored population value
+    size_t state_bytes;
+    size_t off_buf[2];
+    size_t off_wall;  // 6 * lx doubles
+    size_t off_part;  // RED_BLOCKS * 4 doubles, then 2 doubles of loss/dtau scratch
+    size_t off_lam[2];
+    size_t off_apart; // adjoint: one double per collide block
+    size_t total;
+};
+
+Geo make_geo(int lx, int ly, size_t elem)
+{
+    Geo g;
+    g.lx = lx;
+    g.ly = ly;
+    g.g = (int)(128 / elem);                             // 128-byte aligned row 0
+    const int col_align = (int)(128 / elem);
+    g.lyp = (int)align_up((size_t)ly + 2 * g.g, (size_t)col_align);
+    g.origin = (long long)HALO_X * g.lyp + g.g;
+    g.plane = (long long)align_up((size_t)(lx + 2 * HALO_X) * g.lyp * elem, ALIGN) / (long long)elem;
+    return g;
+}
+
+bool valid(const lbm_params* p)
+{
+    if (!p) return false;
+    if (p->lx < 7 || p->ly < 7) return false;
+    if (!(p->tau > 0.5) || !std::isfinite(p->tau) || !std::isfinite(p->g_y)) return false;
+    if (p->precision != LBM_FP64 && p->precision != LBM_FP32_SHIFTED) return false;
+    if (p->ybc != LBM_Y_WALLS && p->ybc != LBM_Y_PERIODIC) return false;
+    if (p->xmode != LBM_X_WRAP && p->xmode != LBM_X_HALO) return false;
+    if (p->step_kind != LBM_STEP_SPLIT && p->step_kind != LBM_STEP_FUSED) return false;
+    if (p->reserved != 0) return false;
+    if ((long long)p->lx * p->ly > (1LL << 31)) return false;
+    return true;
+}
+
+Plan plan(const lbm_params* p)
+{
+    Plan pl{};
+    pl.elem = p->precision == LBM_FP64 ? 8 : 4;
+    pl.geo = make_geo(p->lx, p->ly, pl.elem);
+    pl.lgeo = make_geo(p->lx, p->ly, 8);
+    pl.state_bytes = align_up((size_t)NPOP * pl.geo.plane * pl.elem, ALIGN);
+    size_t off = 0;
+    pl.off_buf[0] = off; off += pl.state_bytes;
+    pl.off_buf[1] = off; off += pl.state_bytes;
+    pl.off_wall = off; off += align_up(6 * (size_t)p->lx * 8, ALIGN);
+    pl.off_part = off; off += align_up(((size_t)RED_BLOCKS * 4 + 2) * 8, ALIGN);
+    if (p->adjoint) {
+        const size_t lb = align_up((size_t)NPOP * pl.lgeo.plane * 8, ALIGN);
+        pl.off_lam[0] = off; off += lb;
+        pl.off_lam[1] = off; off += lb;
+        const size_t nb = (size_t)((p->ly + SITE_THREADS - 1) / SITE_THREADS) * p->lx;
+        pl.off_apart = off; off += align_up(nb * 8, ALIGN);
+    }
+    pl.total = off;
+    return pl;
+}
+
+thread_local std::string g_create_error;
+
+}  // namespace
+
+struct lbm_ctx {
+    lbm_params p;
+    Plan pl;
+    char* ws;
+    hipStream_t stream;
+    int cur;           // current population buffer
+    bool have_prev;    // the other buffer holds the state before the last propagate
+    int lam_cur;
+    bool have_lambda;
+    WallTable wt;
+    CollideArgs cargs;
+    std::string err;
+
+    void* buf(int i) { return ws + pl.off_buf[i]; }
+    double* wall_rho() { return reinterpret_cast<double*>(ws + pl.off_wall); }
+    double* partials() { return reinterpret_cast<double*>(ws + pl.off_part); }
+    double* scratch2() { return partials() + (size_t)RED_BLOCKS * 4; }
+    double* lam(int i) { return reinterpret_cast<double*>(ws + pl.off_lam[i]); }
+    bool fp64() const { return p.precision == LBM_FP64; }
+};
+
+namespace {
+
+lbm_status fail(lbm_ctx* c, lbm_status s, const char* what)
+{
+    c->err = what;
+    return s;
+}
+
+lbm_status check_launch(lbm_ctx* c, const char* what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        c->err = std::string(what) + ": " + hipGetErrorString(e);
+        return LBM_ERR_HIP;
+    }
+    return LBM_OK;
+}
+
+void set_collide_args(lbm_ctx* c)
+{
+    const double tau = c->p.tau, g = c->p.g_y;
+    c->cargs.omega = 1.0 / tau;
+    c->cargs.tau_g = tau * g;
+    c->cargs.grav_th = tau * (1.0 - tau) * g * g / 2.0;
+    c->cargs.omega_f = (float)c->cargs.omega;
+    c->cargs.tau_g_f = (float)c->cargs.tau_g;
+    c->cargs.grav_th_f = (float)c->cargs.grav_th;
+}
+
+dim3 site_grid(const Geo& g) { return dim3((g.ly + SITE_THREADS - 1) / SITE_THREADS, g.lx, 1); }
+
+template <typename S>
+lbm_status launch_propagate(lbm_ctx* c, const S* src, S* dst)
+{
+    const Geo& g = c->pl.geo;
+    constexpr int VEC = sizeof(S) == 8 ? 2 : 4;
+    constexpr int UNROLL = 4;
+    constexpr int CH = PROP_THREADS * VEC * UNROLL;
+    dim3 grid((g.ly + CH - 1) / CH, g.lx, NPOP);
+    if (c->p.xmode == LBM_X_WRAP)
+        hipLaunchKernelGGL((k_propagate<S, VEC, UNROLL, true>), grid, dim3(PROP_THREADS), 0, c->stream, src, dst, g);
+    else
+        hipLaunchKernelGGL((k_propagate<S, VEC, UNROLL, false>), grid, dim3(PROP_THREADS), 0, c->stream, src, dst, g);
+    return check_launch(c, "propagate");
+}
+
+template <typename S>
+lbm_status launch_pre_stream(lbm_ctx* c, S* src)
+{
+    // halos the pull of the current buffer needs: y ghost rows if periodic,
+    // then x halo columns (whole padded columns, so corners follow).
+    const Geo& g = c->pl.geo;
+    if (c->p.ybc == LBM_Y_PERIODIC) {
+        dim3 grid((g.lx * 6 + 255) / 256, NPOP);
+        hipLaunchKernelGGL((k_fill_y_ghosts<S>), grid, dim3(256), 0, c->stream, src, g);
+        lbm_status s = check_launch(c, "fill_y_ghosts");
+        if (s) return s;
+    }
+    if (c->p.xmode == LBM_X_HALO) {
+        dim3 grid((g.lyp + 255) / 256, 3, NPOP);
+        hipLaunchKernelGGL((k_fill_x_halo<S>), grid, dim3(256), 0, c->stream, src, g);
+        lbm_status s = check_launch(c, "fill_x_halo");
+        if (s) return s;
+    }
+    return LBM_OK;
+}
+
+template <typename S>
+lbm_status launch_wall_density(lbm_ctx* c, const S* src)
+{
+    const Geo& g = c->pl.geo;
+    hipLaunchKernelGGL((k_wall_density<S>), dim3((6 * g.lx + 255) / 256), dim3(256), 0, c->stream, src, g, c->wall_rho());
+    return check_launch(c, "wall_density");
+}
+
+template <typename S>
+lbm_status do_propagate(lbm_ctx* c)
+{
+    S* src = (S*)c->buf(c->cur);
+    S* dst = (S*)c->buf(1 - c->cur);
+    lbm_status s = launch_pre_stream<S>(c, src);
+    if (s) return s;
+    s = launch_propagate<S>(c, src, dst);
+    if (s) return s;
+    c->cur = 1 - c->cur;
+    c->have_prev = true;
+    return LBM_OK;
+}
+
+template <typename S>
+lbm_status do_bc(lbm_ctx* c)
+{
+    if (c->p.ybc == LBM_Y_PERIODIC) return LBM_OK;
+    if (!c->have_prev) return fail(c, LBM_ERR_STATE, "bc: no propagate since the state was set");
+    const Geo& g = c->pl.geo;
+    lbm_status s = launch_wall_density<S>(c, (const S*)c->buf(1 - c->cur));
+    if (s) return s;
+    hipLaunchKernelGGL((k_bc_apply<S>), dim3((NSLOT * g.lx + 255) / 256), dim3(256), 0, c->stream,
+                       (S*)c->buf(c->cur), g, (const double*)c->wall_rho(), c->wt);
+    return check_launch(c, "bc_apply");
+}
+
+template <typename S>
+lbm_status do_collide(lbm_ctx* c)
+{
+    const Geo& g = c->pl.geo;
+    hipLaunchKernelGGL((k_collide<S>), site_grid(g), dim3(SITE_THREADS), 0, c->stream, (S*)c->buf(c->cur), g, c->cargs);
+    return check_launch(c, "collide");
+}
+
+template <typename S>
+lbm_status do_step_fused(lbm_ctx* c)
+{
+    const Geo& g = c->pl.geo;
+    S* src = (S*)c->buf(c->cur);
+    S* dst = (S*)c->buf(1 - c->cur);
+    lbm_status s = launch_pre_stream<S>(c, src);
+    if (s) return s;
+    const bool walls = c->p.ybc == LBM_Y_WALLS;
+    if (walls) {
+        s = launch_wall_density<S>(c, src);
+        if (s) return s;
+    }
+    const bool wrap = c->p.xmode == LBM_X_WRAP;
+    const double* wr = c->wall_rho();
+    if (wrap && walls)
+        hipLaunchKernelGGL((k_step_fused<S, true, true>), site_grid(g), dim3(SITE_THREADS), 0, c->stream, src, dst, g, c->cargs, wr, c->wt);
+    else if (wrap)
+        hipLaunchKernelGGL((k_step_fused<S, true, false>), site_grid(g), dim3(SITE_THREADS), 0, c->stream, src, dst, g, c->cargs, wr, c->wt);
+    else if (walls)
+        hipLaunchKernelGGL((k_step_fused<S, false, true>), site_grid(g), dim3(SITE_THREADS), 0, c->stream, src, dst, g, c->cargs, wr, c->wt);
+    else
+        hipLaunchKernelGGL((k_step_fused<S, false, false>), site_grid(g), dim3(SITE_THREADS), 0, c->stream, src, dst, g, c->cargs, wr, c->wt);
+    s = check_launch(c, "step_fused");
+    if (s) return s;
+    c->cur = 1 - c->cur;
+    c->have_prev = true;
+    return LBM_OK;
+}
+
+template <typename S>
+lbm_status do_step(lbm_ctx* c, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        lbm_status s;
+        if (c->p.step_kind == LBM_STEP_FUSED) {
+            s = do_step_fused<S>(c);
+        } else {
+            s = do_propagate<S>(c);
+            if (!s) s = do_bc<S>(c);
+            if (!s) s = do_collide<S>(c);
+        }
+        if (s) return s;
+    }
+    return LBM_OK;
+}
+
+#define DISPATCH(c, fn, ...) ((c)->fp64() ? fn<double>(c, ##__VA_ARGS__) : fn<float>(c, ##__VA_ARGS__))
+
+template <typename S>
+lbm_status do_init(lbm_ctx* c, const double* rho, const double* ux, const double* uy, const double* T)
+{
+    hipLaunchKernelGGL((k_init_fields<S>), site_grid(c->pl.geo), dim3(SITE_THREADS), 0, c->stream,
+                       (S*)c->buf(c->cur), c->pl.geo, rho, ux, uy, T);
+    c->have_prev = false;
+    return check_launch(c, "init");
+}
+template <typename S>
+lbm_status do_init_rt(lbm_ctx* c, const double* P, RtProfile pr)
+{
+    hipLaunchKernelGGL((k_init_rt<S>), site_grid(c->pl.geo), dim3(SITE_THREADS), 0, c->stream,
+                       (S*)c->buf(c->cur), c->pl.geo, P, pr);
+    c->have_prev = false;
+    return check_launch(c, "init_rt");
+}
+template <typename S>
+lbm_status do_macros(lbm_ctx* c, double* rho, double* ux, double* uy, double* T)
+{
+    hipLaunchKernelGGL((k_macros<S>), site_grid(c->pl.geo), dim3(SITE_THREADS), 0, c->stream,
+                       (const S*)c->buf(c->cur), c->pl.geo, rho, ux, uy, T);
+    return check_launch(c, "macros");
+}
+template <typename S>
+lbm_status do_canon(lbm_ctx* c, void* canon, bool to_canon)
+{
+    const Geo& g = c->pl.geo;
+    dim3 grid((g.ly + 255) / 256, g.lx, NPOP);
+    if (to_canon)
+        hipLaunchKernelGGL((k_canon_copy<S, true>), grid, dim3(256), 0, c->stream, (S*)c->buf(c->cur), (S*)canon, g);
+    else
+        hipLaunchKernelGGL((k_canon_copy<S, false>), grid, dim3(256), 0, c->stream, (S*)c->buf(c->cur), (S*)canon, g);
+    if (!to_canon) c->have_prev = false;
+    return check_launch(c, "canonical copy");
+}
+template <typename S>
+lbm_status do_conservation(lbm_ctx* c, double* out4)
+{
+    hipLaunchKernelGGL((k_conservation_partial<S>), dim3(RED_BLOCKS), dim3(256), 0, c->stream,
+                       (const S*)c->buf(c->cur), c->pl.geo, c->partials());
+    lbm_status s = check_launch(c, "conservation");
+    if (s) return s;
+    hipLaunchKernelGGL((k_reduce_partials<4, false>), dim3(1), dim3(256), 0, c->stream,
+                       (const double*)c->partials(), RED_BLOCKS, out4);
+    return check_launch(c, "conservation reduce");
+}
+}  // namespace
+
+// ============================================================================
+// C ABI
+// ============================================================================
+extern "C" {
+
+size_t lbm_workspace_bytes(const lbm_params* p) { return valid(p) ? plan(p).total : 0; }
+
+size_t lbm_state_bytes(const lbm_params* p) { return valid(p) ? plan(p).state_bytes : 0; }
+
+lbm_status lbm_create(const lbm_params* p, void* dev_workspace, size_t bytes, void* hip_stream, lbm_ctx** out)
+{
+    if (!out) { g_create_error = "out is NULL"; return LBM_ERR_INVALID; }
+    *out = nullptr;
+    if (!valid(p)) { g_create_error = "invalid parameters"; return LBM_ERR_INVALID; }
+    Plan pl = plan(p);
+    if (!dev_workspace) { g_create_error = "workspace is NULL"; return LBM_ERR_INVALID; }
+    if ((uintptr_t)dev_workspace % ALIGN) { g_create_error = "workspace not 256-byte aligned"; return LBM_ERR_INVALID; }
+    if (bytes < pl.total) { g_create_error = "workspace too small"; return LBM_ERR_SIZE; }
+    lbm_ctx* c = new lbm_ctx();
+    c->p = *p;
+    c->pl = pl;
+    c->ws = (char*)dev_workspace;
+    c->stream = (hipStream_t)hip_stream;
+    c->cur = 0;
+    c->have_prev = false;
+    c->lam_cur = 0;
+    c->have_lambda = false;
+    for (int l = 0; l < NPOP; ++l) {
+        c->wt.ew[0][l] = feq_pop<false>(l, 1.0, 0.0, 0.0, p->t_bottom);
+        c->wt.ew[1][l] = feq_pop<false>(l, 1.0, 0.0, 0.0, p->t_top);
+        c->wt.w[l] = W_SHELL[SHELL[l]];
+    }
+    set_collide_args(c);
+    if (hipMemsetAsync(dev_workspace, 0, pl.total, c->stream) != hipSuccess) {
+        g_create_error = "hipMemsetAsync of the workspace failed";
+        delete c;
+        return LBM_ERR_HIP;
+    }
+    *out = c;
+    return LBM_OK;
+}
+
+void lbm_destroy(lbm_ctx* ctx) { delete ctx; }
+
+lbm_status lbm_set_tau(lbm_ctx* c, double tau)
+{
+    if (!c) return LBM_ERR_INVALID;
+    if (!(tau > 0.5) || !std::isfinite(tau)) return fail(c, LBM_ERR_INVALID, "tau must be > 0.5");
+    c->p.tau = tau;
+    set_collide_args(c);
+    return LBM_OK;
+}
+
+
+lbm_status lbm_init(lbm_ctx* c, const double* rho, const double* ux, const double* uy, const double* T)
+{
+    if (!c) return LBM_ERR_INVALID;
+    if (!rho || !ux || !uy || !T) return fail(c, LBM_ERR_INVALID, "init: NULL field");
+    return DISPATCH(c, do_init, rho, ux, uy, T);
+}
+
+lbm_status lbm_init_rt(lbm_ctx* c, const double* P, const lbm_rt_profile* prof)
+{
+    if (!c) return LBM_ERR_INVALID;
+    if (!P || !prof) return fail(c, LBM_ERR_INVALID, "init_rt: NULL argument");
+    if (!(prof->width > 0.0) || !(prof->p0 > 0.0)) return fail(c, LBM_ERR_INVALID, "init_rt: width and p0 must be > 0");
+    RtProfile pr{prof->t_mid, prof->t_amp, prof->p0, prof->width, prof->y_mid};
+    return DISPATCH(c, do_init_rt, P, pr);
+}
+
+lbm_status lbm_propagate(lbm_ctx* c)
+{
+    if (!c) return LBM_ERR_INVALID;
+    return DISPATCH(c, do_propagate);
+}
+
+lbm_status lbm_bc(lbm_ctx* c)
+{
+    if (!c) return LBM_ERR_INVALID;
+    return DISPATCH(c, do_bc);
+}
+
+lbm_status lbm_collide(lbm_ctx* c)
+{
+    if (!c) return LBM_ERR_INVALID;
+    return DISPATCH(c, do_collide);
+}
+
+lbm_status lbm_step(lbm_ctx* c, int64_t n)
+{
+    if (!c) return LBM_ERR_INVALID;
+    if (n < 0) return fail(c, LBM_ERR_INVALID, "step: n < 0");
+    return DISPATCH(c, do_step, n);
+}
+
+lbm_status lbm_get_macros(lbm_ctx* c, double* rho, double* ux, double* uy, double* T)
+{
+    if (!c) return LBM_ERR_INVALID;
+    if (!rho || !ux || !uy || !T) return fail(c, LBM_ERR_INVALID, "get_macros: NULL field");
+    return DISPATCH(c, do_macros, rho, ux, uy, T);
+}
+
+lbm_status lbm_get_pops(lbm_ctx* c, void* dst)
+{
+    if (!c) return LBM_ERR_INVALID;
+    if (!dst) return fail(c, LBM_ERR_INVALID, "get_pops: NULL");
+    return DISPATCH(c, do_canon, dst, true);
+}
+
+lbm_status lbm_set_pops(lbm_ctx* c, const void* src)
+{
+    if (!c) return LBM_ERR_INVALID;
+    if (!src) return fail(c, LBM_ERR_INVALID, "set_pops: NULL");
+    return DISPATCH(c, do_canon, const_cast<void*>(src), false);
+}
+
+lbm_status lbm_get_state(lbm_ctx* c, void* dst)
+{
+    if (!c) return LBM_ERR_INVALID;
+    if (!dst) return fail(c, LBM_ERR_INVALID, "get_state: NULL");
+    if (hipMemcpyAsync(dst, c->buf(c->cur), c->pl.state_bytes, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+        return check_launch(c, "get_state");
+    return LBM_OK;
+}
+
+lbm_status lbm_set_state(lbm_ctx* c, const void* src)
+{
+    if (!c) return LBM_ERR_INVALID;
+    if (!src) return fail(c, LBM_ERR_INVALID, "set_state: NULL");
+    if (hipMemcpyAsync(c->buf(c->cur), src, c->pl.state_bytes, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+        return check_launch(c, "set_state");
+    c->have_prev = false;
+    return LBM_OK;
+}
+
+lbm_status lbm_conservation(lbm_ctx* c, double* dev_out4)
+{
+    if (!c) return LBM_ERR_INVALID;
+    if (!dev_out4) return fail(c, LBM_ERR_INVALID, "conservation: NULL");
+    return DISPATCH(c, do_conservation, dev_out4);
+}
+
+lbm_status lbm_sync(lbm_ctx* c)
+{
+    if (!c) return LBM_ERR_INVALID;
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        c->err = std::string("sync: ") + hipGetErrorString(e);
+        return LBM_ERR_HIP;
+    }
+    return LBM_OK;
+}
+
+const char* lbm_last_error(const lbm_ctx* c) { return c ? c->err.c_str() : g_create_error.c_str(); }
+
+void lbm_velocity_table(int8_t ex[LBM_NPOP], int8_t ey[LBM_NPOP])
+{
+    for (int l = 0; l < NPOP; ++l) { ex[l] = (int8_t)EX[l]; ey[l] = (int8_t)EY[l]; }
+}
+
+void lbm_weights(double w[LBM_NPOP])
+{
+    for (int l = 0; l < NPOP; ++l) w[l] = W_SHELL[SHELL[l]];
+}
+
+double lbm_scale_c(void) { return C; }
+
+}  // extern "C"
+
+#include "lbm_adjoint_api.inc"

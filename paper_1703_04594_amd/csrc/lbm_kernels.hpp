@@ -1,0 +1,389 @@
+// lbm_kernels.hpp -- gfx950 kernels of the D2Q37 step (forward).
+//
+// Storage: two population buffers in a padded structure-of-arrays layout.
+// Plane l holds population l of every site; inside a plane the lattice is
+// column-major with y fastest (the paper's column-major choice, section 4),
+// each column padded with G ghost rows on both sides (G * sizeof(S) = 128 B,
+// so interior row 0 of every column is 128-byte aligned) and the plane
+// carries 3 halo columns on both sides (hops reach 3 sites).  Site (x, y) of
+// plane l sits at  l * plane + origin + x * lyp + y.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lbm_site.hpp"
+
+namespace lbm {
+
+struct Geo {
+    int lx, ly;       // interior sites
+    int lyp;          // padded column length (elements)
+    int g;            // ghost rows below / above (elements)
+    long long plane;  // elements per population plane
+    long long origin; // element index of site (0, 0) inside a plane
+};
+
+constexpr int HALO_X = 3;
+
+struct HopTable { int ex[NPOP]; int ey[NPOP]; };
+constexpr HopTable make_hops()
+{
+    HopTable t{};
+    for (int l = 0; l < NPOP; ++l) { t.ex[l] = EX[l]; t.ey[l] = EY[l]; }
+    return t;
+}
+__constant__ HopTable c_hops = make_hops();
+
+// Wall slots: after propagate, slot (l, row r of a wall) pulls from outside
+// the lattice iff the hop towards the interior, e_n = ey (bottom) or -ey
+// (top), exceeds r.  The mirror fluid row is k = e_n - r - 1.  15 + 8 + 3
+// slots per wall and column.
+constexpr int NSLOT = 52;
+struct SlotTable { int l[NSLOT]; int row[NSLOT]; int k[NSLOT]; int wall[NSLOT]; };
+constexpr SlotTable make_slots()
+{
+    SlotTable t{};
+    int n = 0;
+    for (int wall = 0; wall < 2; ++wall)
+        for (int r = 0; r < 3; ++r)
+            for (int l = 0; l < NPOP; ++l) {
+                const int en = wall == 0 ? EY[l] : -EY[l];
+                if (en > r) { t.l[n] = l; t.row[n] = r; t.k[n] = en - r - 1; t.wall[n] = wall; ++n; }
+            }
+    return t;
+}
+static_assert(make_slots().l[NSLOT - 1] != 0, "52 wall slots");
+__constant__ SlotTable c_slots = make_slots();
+
+// f^eq_l(1, 0, T_wall) of both walls, and the weights (for shifted storage).
+struct WallTable { double ew[2][NPOP]; double w[NPOP]; };
+
+template <typename S> struct Store;
+template <> struct Store<double> { using C = double; static constexpr bool shifted = false; };
+template <> struct Store<float>  { using C = float;  static constexpr bool shifted = true; };
+
+__device__ __forceinline__ int wrap_x(int xs, int lx)
+{
+    return xs < 0 ? xs + lx : (xs >= lx ? xs - lx : xs);
+}
+
+// ---------------------------------------------------------------------------
+// propagate: dst_l(x, y) = src_l(x - ex_l, y - ey_l).  One block streams a
+// chunk of one column of one plane; each thread moves UNROLL vectors of VEC
+// elements.  Stores are aligned; loads are shifted by ey elements (unaligned
+// vector loads are legal on CDNA for dword-aligned addresses).
+// ---------------------------------------------------------------------------
+template <typename S, int VEC> struct VecT;
+template <> struct VecT<double, 1> { typedef double T __attribute__((ext_vector_type(1), aligned(8))); };
+template <> struct VecT<double, 2> { typedef double T __attribute__((ext_vector_type(2), aligned(8))); };
+template <> struct VecT<float, 2> { typedef float T __attribute__((ext_vector_type(2), aligned(4))); };
+template <> struct VecT<float, 4> { typedef float T __attribute__((ext_vector_type(4), aligned(4))); };
+template <typename S, int VEC> struct VecA;
+template <> struct VecA<double, 1> { typedef double T __attribute__((ext_vector_type(1))); };
+template <> struct VecA<double, 2> { typedef double T __attribute__((ext_vector_type(2))); };
+template <> struct VecA<float, 2> { typedef float T __attribute__((ext_vector_type(2))); };
+template <> struct VecA<float, 4> { typedef float T __attribute__((ext_vector_type(4))); };
+
+constexpr int PROP_THREADS = 256;
+
+template <typename S, int VEC, int UNROLL, bool WRAP>
+__global__ __launch_bounds__(PROP_THREADS) void k_propagate(const S* __restrict__ src, S* __restrict__ dst, Geo g)
+{
+    using VU = typename VecT<S, VEC>::T;
+    using VA = typename VecA<S, VEC>::T;
+    const int l = blockIdx.z;
+    const int x = blockIdx.y;
+    const int ex = c_hops.ex[l], ey = c_hops.ey[l];
+    int xs = x - ex;
+    if (WRAP) xs = wrap_x(xs, g.lx);
+    const S* sp = src + (size_t)l * g.plane + g.origin + (long long)xs * g.lyp - ey;
+    S* dp = dst + (size_t)l * g.plane + g.origin + (long long)x * g.lyp;
+    const int y0 = blockIdx.x * (PROP_THREADS * VEC * UNROLL) + threadIdx.x * VEC;
+    VU v[UNROLL];
+#pragma unroll
+    for (int u = 0; u < UNROLL; ++u) {
+        const int y = y0 + u * PROP_THREADS * VEC;
+        if (y < g.ly) v[u] = *reinterpret_cast<const VU*>(sp + y);
+    }
+#pragma unroll
+    for (int u = 0; u < UNROLL; ++u) {
+        const int y = y0 + u * PROP_THREADS * VEC;
+        if (y < g.ly) __builtin_nontemporal_store((VA)v[u], reinterpret_cast<VA*>(dp + y));
+    }
+}
+
+// x halos for LBM_X_HALO: copy whole padded columns into the 3 halo columns
+// of each side (only the planes whose hop needs them).  Thread per element.
+template <typename S>
+__global__ __launch_bounds__(256) void k_fill_x_halo(S* __restrict__ buf, Geo g)
+{
+    const int l = blockIdx.z;
+    const int ex = c_hops.ex[l];
+    const int d = blockIdx.y;          // 0..2 -> halo column depth d + 1
+    if (ex == 0 || d >= (ex > 0 ? ex : -ex)) return;
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= g.lyp) return;
+    S* p = buf + (size_t)l * g.plane + g.origin - g.g + i;
+    const int to = ex > 0 ? -(d + 1) : g.lx + d;
+    const int from = ex > 0 ? g.lx - (d + 1) : d;
+    p[(long long)to * g.lyp] = p[(long long)from * g.lyp];
+}
+
+// y ghost rows for LBM_Y_PERIODIC: rows [-3, 0) <- [ly-3, ly), [ly, ly+3) <- [0, 3).
+template <typename S>
+__global__ __launch_bounds__(256) void k_fill_y_ghosts(S* __restrict__ buf, Geo g)
+{
+    const int l = blockIdx.y;
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= g.lx * 6) return;
+    const int x = t / 6, r = t % 6;
+    S* p = buf + (size_t)l * g.plane + g.origin + (long long)x * g.lyp;
+    if (r < 3) p[r - 3] = p[g.ly - 3 + r];
+    else p[g.ly + r - 3] = p[r - 3];
+}
+
+// Density of the 3 rows next to each wall (FP64), for the wall rule.
+// wall_rho[(wall * 3 + k) * lx + x]: bottom row k, top row ly-1-k.
+template <typename S>
+__global__ __launch_bounds__(256) void k_wall_density(const S* __restrict__ buf, Geo g, double* __restrict__ wall_rho)
+{
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= 6 * g.lx) return;
+    const int x = t % g.lx, wk = t / g.lx;
+    const int wall = wk / 3, k = wk % 3;
+    const int y = wall == 0 ? k : g.ly - 1 - k;
+    const S* p = buf + g.origin + (long long)x * g.lyp + y;
+    double r = 0.0;
+#pragma unroll
+    for (int l = 0; l < NPOP; ++l) r += (double)p[(size_t)l * g.plane];
+    wall_rho[t] = Store<S>::shifted ? 1.0 + r : r;
+}
+
+// Wall rule on the current buffer (split step): thread per (column, slot).
+template <typename S>
+__global__ __launch_bounds__(256) void k_bc_apply(S* __restrict__ dst, Geo g, const double* __restrict__ wall_rho, WallTable wt)
+{
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= NSLOT * g.lx) return;
+    const int j = t % NSLOT, x = t / NSLOT;
+    const int l = c_slots.l[j], wall = c_slots.wall[j];
+    const int y = wall == 0 ? c_slots.row[j] : g.ly - 1 - c_slots.row[j];
+    const int xs = wrap_x(x - c_hops.ex[l], g.lx);
+    double v = wt.ew[wall][l] * wall_rho[(wall * 3 + c_slots.k[j]) * g.lx + xs];
+    if (Store<S>::shifted) v -= wt.w[l];
+    dst[(size_t)l * g.plane + g.origin + (long long)x * g.lyp + y] = (S)v;
+}
+
+// ---------------------------------------------------------------------------
+// collide: one thread per site, in place.
+// ---------------------------------------------------------------------------
+constexpr int SITE_THREADS = 256;
+
+template <typename S>
+__global__ __launch_bounds__(SITE_THREADS) void k_collide(S* __restrict__ buf, Geo g, CollideArgs args)
+{
+    using Cc = typename Store<S>::C;
+    const int x = blockIdx.y;
+    const int y = blockIdx.x * SITE_THREADS + threadIdx.x;
+    if (y >= g.ly) return;
+    S* p = buf + g.origin + (long long)x * g.lyp + y;
+    Cc f[NPOP];
+#pragma unroll
+    for (int l = 0; l < NPOP; ++l) f[l] = (Cc)p[(size_t)l * g.plane];
+    collide_site<Cc, Store<S>::shifted>(f, args);
+#pragma unroll
+    for (int l = 0; l < NPOP; ++l) __builtin_nontemporal_store((S)f[l], p + (size_t)l * g.plane);
+}
+
+// ---------------------------------------------------------------------------
+// Fused step: gather (eq. (4) pull) + wall rule + collide, src -> dst.
+// ---------------------------------------------------------------------------
+template <typename S, bool WRAP, bool WALLS>
+__global__ __launch_bounds__(SITE_THREADS) void k_step_fused(const S* __restrict__ src, S* __restrict__ dst, Geo g,
+                                                          CollideArgs args, const double* __restrict__ wall_rho, WallTable wt)
+{
+    using Cc = typename Store<S>::C;
+    const int x = blockIdx.y;
+    const int y = blockIdx.x * SITE_THREADS + threadIdx.x;
+    if (y >= g.ly) return;
+    Cc f[NPOP];
+#pragma unroll
+    for (int l = 0; l < NPOP; ++l) {
+        int xs = x - EX[l];
+        if (WRAP) xs = wrap_x(xs, g.lx);
+        f[l] = (Cc)src[(size_t)l * g.plane + g.origin + (long long)xs * g.lyp + (y - EY[l])];
+    }
+    if (WALLS && (y < 3 || y >= g.ly - 3)) {
+#pragma unroll
+        for (int l = 0; l < NPOP; ++l) {
+            if (EY[l] == 0) continue;
+            const int wall = EY[l] > 0 ? 0 : 1;
+            const int r = wall == 0 ? y : g.ly - 1 - y;       // row counted from the wall
+            const int en = wall == 0 ? EY[l] : -EY[l];
+            if (en > r) {
+                const int xs = wrap_x(x - EX[l], g.lx);
+                double v = wt.ew[wall][l] * wall_rho[(wall * 3 + (en - r - 1)) * g.lx + xs];
+                if (Store<S>::shifted) v -= wt.w[l];
+                f[l] = (Cc)v;
+            }
+        }
+    }
+    collide_site<Cc, Store<S>::shifted>(f, args);
+    S* p = dst + g.origin + (long long)x * g.lyp + y;
+#pragma unroll
+    for (int l = 0; l < NPOP; ++l) __builtin_nontemporal_store((S)f[l], p + (size_t)l * g.plane);
+}
+
+// ---------------------------------------------------------------------------
+// Initial states, read-out, copies.
+// ---------------------------------------------------------------------------
+template <typename S>
+__global__ __launch_bounds__(SITE_THREADS) void k_init_fields(S* __restrict__ buf, Geo g, const double* __restrict__ rho,
+                                                           const double* __restrict__ ux, const double* __restrict__ uy,
+                                                           const double* __restrict__ T)
+{
+    const int x = blockIdx.y;
+    const int y = blockIdx.x * SITE_THREADS + threadIdx.x;
+    if (y >= g.ly) return;
+    const long long s = (long long)x * g.ly + y;
+    const double r = rho[s], vx = ux[s], vy = uy[s], t = T[s];
+    S* p = buf + g.origin + (long long)x * g.lyp + y;
+#pragma unroll
+    for (int l = 0; l < NPOP; ++l) p[(size_t)l * g.plane] = (S)feq_pop<Store<S>::shifted>(l, r, vx, vy, t);
+}
+
+struct RtProfile { double t_mid, t_amp, p0, width, y_mid; };
+
+template <typename S>
+__global__ __launch_bounds__(SITE_THREADS) void k_init_rt(S* __restrict__ buf, Geo g, const double* __restrict__ P, RtProfile pr)
+{
+    const int x = blockIdx.y;
+    const int y = blockIdx.x * SITE_THREADS + threadIdx.x;
+    if (y >= g.ly) return;
+    const double T0 = pr.t_mid - pr.t_amp * tanh((y - pr.y_mid - P[(long long)x * g.ly + y]) / pr.width);
+    const double r0 = pr.p0 / T0;
+    S* p = buf + g.origin + (long long)x * g.lyp + y;
+#pragma unroll
+    for (int l = 0; l < NPOP; ++l) p[(size_t)l * g.plane] = (S)feq_pop<Store<S>::shifted>(l, r0, 0.0, 0.0, T0);
+}
+
+// rho, u, T of eq. (2) in FP64.  Shifted storage uses the deviation form
+// rho = 1 + sum d, T - 1 = (sum (x2 - 2) d) / (2 rho) - u2 / 2.
+template <typename S>
+__device__ __forceinline__ void site_macros(const S* p, long long plane, double& rho, double& ux, double& uy, double& T)
+{
+    double f[NPOP];
+#pragma unroll
+    for (int l = 0; l < NPOP; ++l) f[l] = (double)p[(size_t)l * plane];
+    double m0, sx, sy, s2;
+    hop_moments<double>(f, m0, sx, sy, s2);
+    if (Store<S>::shifted) {
+        rho = 1.0 + m0;
+        ux = C * sx / rho;
+        uy = C * sy / rho;
+        T = 1.0 + (C2 * s2 - 2.0 * m0) / (2.0 * rho) - 0.5 * (ux * ux + uy * uy);
+    } else {
+        rho = m0;
+        ux = C * sx / rho;
+        uy = C * sy / rho;
+        T = 0.5 * (C2 * s2 / rho - (ux * ux + uy * uy));
+    }
+}
+
+template <typename S>
+__global__ __launch_bounds__(SITE_THREADS) void k_macros(const S* __restrict__ buf, Geo g, double* __restrict__ rho,
+                                                      double* __restrict__ ux, double* __restrict__ uy, double* __restrict__ T)
+{
+    const int x = blockIdx.y;
+    const int y = blockIdx.x * SITE_THREADS + threadIdx.x;
+    if (y >= g.ly) return;
+    double r, vx, vy, t;
+    site_macros<S>(buf + g.origin + (long long)x * g.lyp + y, g.plane, r, vx, vy, t);
+    const long long s = (long long)x * g.ly + y;
+    rho[s] = r; ux[s] = vx; uy[s] = vy; T[s] = t;
+}
+
+// canonical [37][lx][ly] <-> padded, thread per element
+template <typename S, bool TO_CANON>
+__global__ __launch_bounds__(256) void k_canon_copy(S* __restrict__ buf, S* __restrict__ canon, Geo g)
+{
+    const int l = blockIdx.z, x = blockIdx.y;
+    const int y = blockIdx.x * 256 + threadIdx.x;
+    if (y >= g.ly) return;
+    const size_t pi = (size_t)l * g.plane + g.origin + (long long)x * g.lyp + y;
+    const size_t ci = ((size_t)l * g.lx + x) * g.ly + y;
+    if (TO_CANON) canon[ci] = buf[pi];
+    else buf[pi] = canon[ci];
+}
+
+// ---------------------------------------------------------------------------
+// Deterministic FP64 reductions: fixed grid, wave shuffles in fixed order,
+// LDS across waves, then one block over the partials.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+template <int N>
+__device__ __forceinline__ void block_sum_store(double (&v)[N], double* __restrict__ out)
+{
+    __shared__ double red[N][256 / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        const double s = wave_sum(v[i]);
+        if (lane == 0) red[i][wid] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < N) {
+        double s = 0.0;
+        for (int w = 0; w < 256 / 64; ++w) s += red[threadIdx.x][w];
+        out[threadIdx.x] = s;
+    }
+}
+
+constexpr int RED_BLOCKS = 1024;
+
+template <typename S>
+__global__ __launch_bounds__(256) void k_conservation_partial(const S* __restrict__ buf, Geo g, double* __restrict__ partials)
+{
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    const long long n = (long long)g.lx * g.ly;
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+        const int x = (int)(i / g.ly), y = (int)(i % g.ly);
+        const S* p = buf + g.origin + (long long)x * g.lyp + y;
+        double f[NPOP];
+#pragma unroll
+        for (int l = 0; l < NPOP; ++l) f[l] = (double)p[(size_t)l * g.plane];
+        double m0, sx, sy, s2;
+        hop_moments<double>(f, m0, sx, sy, s2);
+        acc[0] += Store<S>::shifted ? 1.0 + m0 : m0;
+        acc[1] += C * sx;
+        acc[2] += C * sy;
+        acc[3] += Store<S>::shifted ? 2.0 + C2 * s2 : C2 * s2;
+    }
+    block_sum_store<4>(acc, partials + (size_t)blockIdx.x * 4);
+}
+
+// out[k] (+)= sum over nparts of partials[p * N + k], one block, fixed order.
+template <int N, bool ACCUMULATE>
+__global__ __launch_bounds__(256) void k_reduce_partials(const double* __restrict__ partials, int nparts, double* __restrict__ out)
+{
+    double v[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) v[k] = 0.0;
+    for (int p = threadIdx.x; p < nparts; p += 256) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) v[k] += partials[(size_t)p * N + k];
+    }
+    __shared__ double tot[N];
+    block_sum_store<N>(v, tot);
+    __syncthreads();
+    if (threadIdx.x < N) out[threadIdx.x] = ACCUMULATE ? out[threadIdx.x] + tot[threadIdx.x] : tot[threadIdx.x];
+}
+
+}  // namespace lbm

@@ -1,0 +1,174 @@
+// lbm_site.hpp -- per-site arithmetic of the D2Q37 step on gfx950.
+//
+// arXiv:1703.04594, section 3: moments of eq. (2), BGK relaxation of
+// eq. (1) towards the 4th-order Hermite equilibrium, with gravity entering as
+// a shift of the equilibrium's velocity and temperature.  Two storage forms:
+//  - absolute:  f_l, computed in FP64;
+//  - shifted:   d_l = f_l - w_l (deviation from the rest state rho = 1, u = 0,
+//               T = 1, whose equilibrium is w_l), computed in FP32.  All sums
+//               are of deviations, so their rounding error scales with the
+//               departure from rest, not with the populations themselves.
+//
+// The equilibrium is evaluated per site in Horner form in a = xi_l . u:
+//   f^eq_l = w_l rho (A0 + a (A1 + a (A2 + a (1/6 + a/24))))
+// with shell coefficients (x2 = |xi|^2, th = T - 1, u2 = |u|^2)
+//   A0 = 1 - u2/2 + u2^2/8 + th ((x2-2)/2 + u2 (4-x2)/4 + th (x2^2-8x2+8)/8)
+//   A1 = 1 - u2/2 + th (x2-4)/2
+//   A2 = 1/2 - u2/4 + th (x2-6)/4
+// which is the expanded 4th-order Hermite expansion regrouped by powers of a.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "d2q37_tables.h"
+
+namespace lbm {
+
+using namespace d2q37;
+
+constexpr int R2_OF(int l) { return EX[l] * EX[l] + EY[l] * EY[l]; }
+
+// Shell constants of the Hermite coefficients, evaluated at compile time.
+template <typename C> struct ShellK {
+    static constexpr C x2(int s) { return C(SHELL_R2[s]) * C(C2); }
+    static constexpr C k1(int s) { return (C(C2) * C(SHELL_R2[s]) - C(2)) / C(2); }
+    static constexpr C k2(int s) { return (C(4) - C(C2) * C(SHELL_R2[s])) / C(4); }
+    static constexpr C k3(int s) {
+        return (C(C2) * C(SHELL_R2[s]) * C(C2) * C(SHELL_R2[s]) - C(8) * C(C2) * C(SHELL_R2[s]) + C(8)) / C(8);
+    }
+    static constexpr C k4(int s) { return (C(C2) * C(SHELL_R2[s]) - C(4)) / C(2); }
+    static constexpr C k5(int s) { return (C(C2) * C(SHELL_R2[s]) - C(6)) / C(4); }
+};
+
+template <typename C> __device__ __host__ constexpr C wshell(int s);
+template <> __device__ __host__ constexpr double wshell<double>(int s) { return W_SHELL[s]; }
+template <> __device__ __host__ constexpr float wshell<float>(int s) { return W_SHELL_F[s]; }
+template <typename C> __device__ __host__ constexpr C cscale();
+template <> __device__ __host__ constexpr double cscale<double>() { return C; }
+template <> __device__ __host__ constexpr float cscale<float>() { return C_F; }
+template <typename C> __device__ __host__ constexpr C c2scale();
+template <> __device__ __host__ constexpr double c2scale<double>() { return C2; }
+template <> __device__ __host__ constexpr float c2scale<float>() { return C2_F; }
+
+// Integer-hop moments: m0 = sum f, sx = sum ex f, sy = sum ey f,
+// s2 = sum |e|^2 f.  Zero hop components are skipped at compile time.
+template <typename C>
+__device__ __forceinline__ void hop_moments(const C (&f)[NPOP], C& m0, C& sx, C& sy, C& s2)
+{
+    m0 = C(0); sx = C(0); sy = C(0); s2 = C(0);
+#pragma unroll
+    for (int l = 0; l < NPOP; ++l) {
+        m0 += f[l];
+        if (EX[l] != 0) sx += C(EX[l]) * f[l];
+        if (EY[l] != 0) sy += C(EY[l]) * f[l];
+        if (R2_OF(l) != 0) s2 += C(R2_OF(l)) * f[l];
+    }
+}
+
+template <typename C>
+__device__ __forceinline__ C hop_dot(int l, C cux, C cuy)
+{
+    C a = C(0);
+    if (EX[l] != 0 && EY[l] != 0) a = C(EX[l]) * cux + C(EY[l]) * cuy;
+    else if (EX[l] != 0) a = C(EX[l]) * cux;
+    else if (EY[l] != 0) a = C(EY[l]) * cuy;
+    return a;
+}
+
+struct CollideArgs {
+    double omega;    // 1 / tau
+    double tau_g;    // tau * g_y   (velocity shift)
+    double grav_th;  // tau (1 - tau) g_y^2 / 2   (temperature shift)
+    float omega_f, tau_g_f, grav_th_f;
+};
+
+template <typename C> __device__ __forceinline__ C arg_omega(const CollideArgs& a);
+template <> __device__ __forceinline__ double arg_omega<double>(const CollideArgs& a) { return a.omega; }
+template <> __device__ __forceinline__ float arg_omega<float>(const CollideArgs& a) { return a.omega_f; }
+template <typename C> __device__ __forceinline__ C arg_taug(const CollideArgs& a);
+template <> __device__ __forceinline__ double arg_taug<double>(const CollideArgs& a) { return a.tau_g; }
+template <> __device__ __forceinline__ float arg_taug<float>(const CollideArgs& a) { return a.tau_g_f; }
+template <typename C> __device__ __forceinline__ C arg_gth(const CollideArgs& a);
+template <> __device__ __forceinline__ double arg_gth<double>(const CollideArgs& a) { return a.grav_th; }
+template <> __device__ __forceinline__ float arg_gth<float>(const CollideArgs& a) { return a.grav_th_f; }
+
+// BGK collision of one site, in place.  SHIFTED: f holds deviations d_l.
+template <typename C, bool SHIFTED>
+__device__ __forceinline__ void collide_site(C (&f)[NPOP], const CollideArgs& args)
+{
+    using K = ShellK<C>;
+    const C omega = arg_omega<C>(args);
+    C m0, sx, sy, s2;
+    hop_moments<C>(f, m0, sx, sy, s2);
+    const C rho = SHIFTED ? C(1) + m0 : m0;
+    const C inv = C(1) / rho;
+    const C ux = cscale<C>() * sx * inv;
+    C uy = cscale<C>() * sy * inv;
+    C th;
+    if constexpr (SHIFTED) {
+        // T - 1 = (sum (x2 - 2) d) / (2 rho) - u2 / 2
+        th = (c2scale<C>() * s2 - C(2) * m0) * inv * C(0.5) - (ux * ux + uy * uy) * C(0.5);
+    } else {
+        th = (c2scale<C>() * s2 * inv - (ux * ux + uy * uy)) * C(0.5) - C(1);
+    }
+    uy += arg_taug<C>(args);
+    th += arg_gth<C>(args);
+    const C u2 = ux * ux + uy * uy;
+    const C cux = cscale<C>() * ux, cuy = cscale<C>() * uy;
+    // shell-independent parts
+    const C b1 = C(1) - C(0.5) * u2;             // A1 without th
+    const C b2 = C(0.5) - C(0.25) * u2;          // A2 without th
+    const C b0m1 = u2 * (C(-0.5) + C(0.125) * u2); // A0 - 1 without th
+    C A0m1[NSHELL], A1[NSHELL], A2[NSHELL];
+#pragma unroll
+    for (int s = 0; s < NSHELL; ++s) {
+        A0m1[s] = b0m1 + th * (K::k1(s) + u2 * K::k2(s) + th * K::k3(s));
+        A1[s] = b1 + th * K::k4(s);
+        A2[s] = b2 + th * K::k5(s);
+    }
+#pragma unroll
+    for (int l = 0; l < NPOP; ++l) {
+        const int s = SHELL[l];
+        C pm;   // P - 1 = A0 - 1 + a (A1 + a (A2 + a (1/6 + a/24)))
+        if (l == 0) {
+            pm = A0m1[0];
+        } else {
+            const C a = hop_dot<C>(l, cux, cuy);
+            C t = a * C(1.0 / 24.0) + C(1.0 / 6.0);
+            t = t * a + A2[s];
+            t = t * a + A1[s];
+            pm = t * a + A0m1[s];
+        }
+        C feq;
+        if constexpr (SHIFTED) {
+            // d^eq = w ((rho - 1) P + (P - 1)) = w (m0 + rho (P - 1))
+            feq = wshell<C>(s) * (m0 + rho * pm);
+        } else {
+            feq = wshell<C>(s) * rho * (C(1) + pm);
+        }
+        f[l] = f[l] + omega * (feq - f[l]);
+    }
+}
+
+// Equilibrium of given fields, FP64 (initial states and wall tables).
+// Returns f^eq_l - w_l when SHIFTED, f^eq_l otherwise.
+template <bool SHIFTED>
+__device__ __host__ __forceinline__ double feq_pop(int l, double rho, double ux, double uy, double T)
+{
+    using K = ShellK<double>;
+    const int s = SHELL[l];
+    const double th = T - 1.0;
+    const double u2 = ux * ux + uy * uy;
+    const double a = C * (EX[l] * ux + EY[l] * uy);
+    const double A0m1 = u2 * (-0.5 + 0.125 * u2) + th * (K::k1(s) + u2 * K::k2(s) + th * K::k3(s));
+    const double A1 = 1.0 - 0.5 * u2 + th * K::k4(s);
+    const double A2 = 0.5 - 0.25 * u2 + th * K::k5(s);
+    double t = a * (1.0 / 24.0) + 1.0 / 6.0;
+    t = t * a + A2;
+    t = t * a + A1;
+    const double pm = t * a + A0m1;
+    if (SHIFTED) return W_SHELL[s] * ((rho - 1.0) + rho * pm);
+    return W_SHELL[s] * rho * (1.0 + pm);
+}
+
+}  // namespace lbm

@@ -11,8 +11,9 @@ Recipes (all FP64, numpy ``default_rng`` streams keyed by an integer seed):
   scaled by the amplitude (1e-3 lattice units) and repeated along y.
 * ``population_noise`` -- standard normal numbers in the canonical population
   layout [37][lx][ly], used to build non-equilibrium test states.
-* ``probe_directions`` -- k unit-norm standard normal fields of shape
-  (lx, ly) for directional finite-difference checks.
+* ``probe_directions`` -- k standard normal fields of shape (lx, ly) for
+  directional finite-difference checks, scaled to unit 2-norm ("l2") or to
+  unit root-mean-square per site ("rms").
 * ``uniform_field`` -- uniform numbers in [lo, hi) of shape (lx, ly).
 """
 from __future__ import annotations
@@ -33,10 +34,12 @@ def population_noise(lx: int, ly: int, seed: int) -> np.ndarray:
     return rng.standard_normal((NPOP, lx, ly))
 
 
-def probe_directions(lx: int, ly: int, seed: int, k: int) -> np.ndarray:
+def probe_directions(lx: int, ly: int, seed: int, k: int, norm: str = "l2") -> np.ndarray:
     rng = np.random.default_rng(seed)
     v = rng.standard_normal((k, lx, ly))
     v /= np.sqrt((v * v).sum(axis=(1, 2), keepdims=True))
+    if norm == "rms":
+        v *= np.sqrt(lx * ly)
     return v
 
 

@@ -1,0 +1,289 @@
+"""Python binding of liblbm.so (include/lbm.h): argument marshalling only.
+
+Device memory and streams come from PyTorch: the workspace is a uint8 CUDA
+tensor, every array argument is a contiguous CUDA tensor of the documented
+dtype and shape, and all work is enqueued on the stream that was current when
+the Lattice was created.  Every computation runs in the library's kernels;
+if the library is missing this module raises instead of computing anything.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblbm.so")
+
+NPOP = 37
+FP64, FP32_SHIFTED = 0, 1
+Y_WALLS, Y_PERIODIC = 0, 1
+X_WRAP, X_HALO = 0, 1
+STEP_SPLIT, STEP_FUSED = 0, 1
+
+_PREC = {"fp64": FP64, "fp32": FP32_SHIFTED, "fp32_shifted": FP32_SHIFTED}
+_YBC = {"walls": Y_WALLS, "periodic": Y_PERIODIC}
+_XMODE = {"wrap": X_WRAP, "halo": X_HALO}
+_STEP = {"split": STEP_SPLIT, "fused": STEP_FUSED}
+
+
+class LBMError(RuntimeError):
+    pass
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("lx", ctypes.c_int32), ("ly", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("ybc", ctypes.c_int32), ("xmode", ctypes.c_int32), ("step_kind", ctypes.c_int32),
+                ("adjoint", ctypes.c_int32), ("reserved", ctypes.c_int32), ("tau", ctypes.c_double),
+                ("g_y", ctypes.c_double), ("t_bottom", ctypes.c_double), ("t_top", ctypes.c_double)]
+
+
+class RtProfileC(ctypes.Structure):
+    _fields_ = [("t_mid", ctypes.c_double), ("t_amp", ctypes.c_double), ("p0", ctypes.c_double),
+                ("width", ctypes.c_double), ("y_mid", ctypes.c_double)]
+
+
+@dataclass
+class RtProfile:
+    """T0 = t_mid - t_amp tanh((y - y_mid - P) / width), rho0 = p0 / T0."""
+    t_mid: float = 1.0
+    t_amp: float = 1.0 / 3.0
+    p0: float = 8.0 / 9.0
+    width: float = 2.0
+    y_mid: float | None = None   # default (ly - 1) / 2
+
+    def c(self, ly: int) -> RtProfileC:
+        ym = (ly - 1) / 2.0 if self.y_mid is None else self.y_mid
+        return RtProfileC(self.t_mid, self.t_amp, self.p0, self.width, ym)
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise LBMError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                       "(the library has no CPU fallback)")
+    # torch first, so that liblbm binds to the HIP runtime torch already loaded
+    import torch  # noqa: F401
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, d, st = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int
+    PP = ctypes.POINTER(Params)
+    L.lbm_workspace_bytes.argtypes = [PP]
+    L.lbm_workspace_bytes.restype = ctypes.c_size_t
+    L.lbm_state_bytes.argtypes = [PP]
+    L.lbm_state_bytes.restype = ctypes.c_size_t
+    L.lbm_create.argtypes = [PP, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
+    L.lbm_destroy.argtypes = [vp]
+    L.lbm_destroy.restype = None
+    L.lbm_set_tau.argtypes = [vp, d]
+    L.lbm_init.argtypes = [vp, vp, vp, vp, vp]
+    L.lbm_init_rt.argtypes = [vp, vp, ctypes.POINTER(RtProfileC)]
+    for n in ("lbm_propagate", "lbm_bc", "lbm_collide", "lbm_sync"):
+        getattr(L, n).argtypes = [vp]
+    L.lbm_step.argtypes = [vp, i64]
+    L.lbm_get_macros.argtypes = [vp, vp, vp, vp, vp]
+    for n in ("lbm_get_pops", "lbm_set_pops", "lbm_get_state", "lbm_set_state", "lbm_conservation",
+              "lbm_adjoint_seed_temperature", "lbm_adjoint_get_lambda", "lbm_adjoint_set_lambda"):
+        getattr(L, n).argtypes = [vp, vp]
+    L.lbm_loss_temperature.argtypes = [vp, vp, vp]
+    L.lbm_adjoint_step.argtypes = [vp, vp, vp]
+    L.lbm_adjoint_init_rt.argtypes = [vp, vp, ctypes.POINTER(RtProfileC), vp]
+    L.lbm_last_error.argtypes = [vp]
+    L.lbm_last_error.restype = ctypes.c_char_p
+    L.lbm_velocity_table.argtypes = [ctypes.POINTER(ctypes.c_int8), ctypes.POINTER(ctypes.c_int8)]
+    L.lbm_velocity_table.restype = None
+    L.lbm_weights.argtypes = [ctypes.POINTER(ctypes.c_double)]
+    L.lbm_weights.restype = None
+    L.lbm_scale_c.restype = ctypes.c_double
+    for n in ("lbm_create", "lbm_set_tau", "lbm_init", "lbm_init_rt", "lbm_propagate", "lbm_bc",
+              "lbm_collide", "lbm_step", "lbm_get_macros", "lbm_get_pops", "lbm_set_pops",
+              "lbm_get_state", "lbm_set_state", "lbm_conservation", "lbm_loss_temperature",
+              "lbm_adjoint_seed_temperature", "lbm_adjoint_step", "lbm_adjoint_init_rt",
+              "lbm_adjoint_get_lambda", "lbm_adjoint_set_lambda", "lbm_sync"):
+        getattr(L, n).restype = st
+    _lib = L
+    return L
+
+
+def velocity_table():
+    ex = (ctypes.c_int8 * NPOP)()
+    ey = (ctypes.c_int8 * NPOP)()
+    lib().lbm_velocity_table(ex, ey)
+    return list(ex), list(ey)
+
+
+def weights():
+    w = (ctypes.c_double * NPOP)()
+    lib().lbm_weights(w)
+    return list(w)
+
+
+def scale_c() -> float:
+    return float(lib().lbm_scale_c())
+
+
+def make_params(lx, ly, tau, g_y=0.0, t_bottom=1.0, t_top=1.0, precision="fp64", ybc="walls",
+                xmode="wrap", step="split", adjoint=False) -> Params:
+    return Params(lx, ly, _PREC[precision], _YBC[ybc], _XMODE[xmode], _STEP[step], int(bool(adjoint)), 0,
+                  tau, g_y, t_bottom, t_top)
+
+
+def workspace_bytes(p: Params) -> int:
+    return int(lib().lbm_workspace_bytes(ctypes.byref(p)))
+
+
+def _ptr(t: torch.Tensor, dtype, shape, device) -> int:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch tensor")
+    if t.dtype != dtype or tuple(t.shape) != tuple(shape) or not t.is_contiguous() or t.device != device:
+        raise ValueError(f"expected contiguous {dtype} {tuple(shape)} on {device}, got "
+                         f"{t.dtype} {tuple(t.shape)} on {t.device}")
+    return t.data_ptr()
+
+
+class Lattice:
+    """One D2Q37 lattice on one GPU (a context of liblbm.so)."""
+
+    def __init__(self, lx, ly, tau, g_y=0.0, t_bottom=1.0, t_top=1.0, precision="fp64",
+                 ybc="walls", xmode="wrap", step="split", adjoint=False, device="cuda"):
+        self.L = lib()
+        self.device = torch.device(device)
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        self.p = make_params(lx, ly, tau, g_y, t_bottom, t_top, precision, ybc, xmode, step, adjoint)
+        self.lx, self.ly = lx, ly
+        self.precision = precision
+        self.store_dtype = torch.float64 if _PREC[precision] == FP64 else torch.float32
+        nbytes = workspace_bytes(self.p)
+        if nbytes == 0:
+            raise LBMError("invalid lattice parameters")
+        self.state_bytes = int(self.L.lbm_state_bytes(ctypes.byref(self.p)))
+        with torch.cuda.device(self.device):
+            self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            self.stream = torch.cuda.current_stream(self.device)
+        base = self.workspace.data_ptr()
+        self._ws_ptr = (base + 255) // 256 * 256
+        h = ctypes.c_void_p()
+        st = self.L.lbm_create(ctypes.byref(self.p), ctypes.c_void_p(self._ws_ptr), nbytes,
+                               ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        if st != 0:
+            raise LBMError(f"lbm_create: {self.L.lbm_last_error(None).decode()} (status {st})")
+        self.h = h
+
+    # ------------------------------------------------------------------
+    def _check(self, st: int, what: str):
+        if st != 0:
+            raise LBMError(f"{what}: {self.L.lbm_last_error(self.h).decode()} (status {st})")
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.lbm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _field(self, t):
+        return ctypes.c_void_p(_ptr(t, torch.float64, (self.lx, self.ly), self.device))
+
+    def _new_field(self):
+        return torch.empty((self.lx, self.ly), dtype=torch.float64, device=self.device)
+
+    # ------------------------------------------------------------------
+    def set_tau(self, tau: float):
+        self._check(self.L.lbm_set_tau(self.h, tau), "set_tau")
+
+    def init(self, rho, ux, uy, T):
+        self._check(self.L.lbm_init(self.h, self._field(rho), self._field(ux), self._field(uy),
+                                    self._field(T)), "init")
+
+    def init_rt(self, P, profile: RtProfile | None = None):
+        prof = (profile or RtProfile()).c(self.ly)
+        self._check(self.L.lbm_init_rt(self.h, self._field(P), ctypes.byref(prof)), "init_rt")
+
+    def propagate(self):
+        self._check(self.L.lbm_propagate(self.h), "propagate")
+
+    def bc(self):
+        self._check(self.L.lbm_bc(self.h), "bc")
+
+    def collide(self):
+        self._check(self.L.lbm_collide(self.h), "collide")
+
+    def step(self, n: int = 1):
+        self._check(self.L.lbm_step(self.h, int(n)), "step")
+
+    def macros(self):
+        out = [self._new_field() for _ in range(4)]
+        self._check(self.L.lbm_get_macros(self.h, *[ctypes.c_void_p(t.data_ptr()) for t in out]), "get_macros")
+        return tuple(out)
+
+    def get_pops(self) -> torch.Tensor:
+        out = torch.empty((NPOP, self.lx, self.ly), dtype=self.store_dtype, device=self.device)
+        self._check(self.L.lbm_get_pops(self.h, ctypes.c_void_p(out.data_ptr())), "get_pops")
+        return out
+
+    def set_pops(self, f: torch.Tensor):
+        p = _ptr(f, self.store_dtype, (NPOP, self.lx, self.ly), self.device)
+        self._check(self.L.lbm_set_pops(self.h, ctypes.c_void_p(p)), "set_pops")
+
+    def new_state(self) -> torch.Tensor:
+        return torch.empty(self.state_bytes, dtype=torch.uint8, device=self.device)
+
+    def get_state(self, out: torch.Tensor | None = None) -> torch.Tensor:
+        out = self.new_state() if out is None else out
+        p = _ptr(out, torch.uint8, (self.state_bytes,), self.device)
+        self._check(self.L.lbm_get_state(self.h, ctypes.c_void_p(p)), "get_state")
+        return out
+
+    def set_state(self, s: torch.Tensor):
+        p = _ptr(s, torch.uint8, (self.state_bytes,), self.device)
+        self._check(self.L.lbm_set_state(self.h, ctypes.c_void_p(p)), "set_state")
+
+    def conservation(self) -> torch.Tensor:
+        out = torch.empty(4, dtype=torch.float64, device=self.device)
+        self._check(self.L.lbm_conservation(self.h, ctypes.c_void_p(out.data_ptr())), "conservation")
+        return out
+
+    # -- adjoint ----------------------------------------------------------
+    def loss_temperature(self, T_target) -> torch.Tensor:
+        out = torch.empty((), dtype=torch.float64, device=self.device)
+        self._check(self.L.lbm_loss_temperature(self.h, self._field(T_target), ctypes.c_void_p(out.data_ptr())),
+                    "loss_temperature")
+        return out
+
+    def seed_temperature(self, dT):
+        self._check(self.L.lbm_adjoint_seed_temperature(self.h, self._field(dT)), "seed_temperature")
+
+    def adjoint_step(self, state: torch.Tensor, dtau_acc: torch.Tensor):
+        p = _ptr(state, torch.uint8, (self.state_bytes,), self.device)
+        a = _ptr(dtau_acc, torch.float64, (), self.device)
+        self._check(self.L.lbm_adjoint_step(self.h, ctypes.c_void_p(p), ctypes.c_void_p(a)), "adjoint_step")
+
+    def adjoint_init_rt(self, P, profile: RtProfile | None = None) -> torch.Tensor:
+        prof = (profile or RtProfile()).c(self.ly)
+        out = self._new_field()
+        self._check(self.L.lbm_adjoint_init_rt(self.h, self._field(P), ctypes.byref(prof),
+                                               ctypes.c_void_p(out.data_ptr())), "adjoint_init_rt")
+        return out
+
+    def get_lambda(self) -> torch.Tensor:
+        out = torch.empty((NPOP, self.lx, self.ly), dtype=torch.float64, device=self.device)
+        self._check(self.L.lbm_adjoint_get_lambda(self.h, ctypes.c_void_p(out.data_ptr())), "get_lambda")
+        return out
+
+    def set_lambda(self, lam: torch.Tensor):
+        p = _ptr(lam, torch.float64, (NPOP, self.lx, self.ly), self.device)
+        self._check(self.L.lbm_adjoint_set_lambda(self.h, ctypes.c_void_p(p)), "set_lambda")
+
+    def sync(self):
+        self._check(self.L.lbm_sync(self.h), "sync")

@@ -1,0 +1,67 @@
+"""The C-ABI library loads, exports every symbol of include/lbm.h, agrees
+with the oracle on the lattice constants, and validates arguments on the
+host (CPU only: no call here reaches the device)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1703_04594_amd import lbm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "lbm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported():
+    L = lbm.lib()
+    names = declared_functions()
+    assert len(names) == 28
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_constants_match_the_oracle_bitwise():
+    ex, ey = lbm.velocity_table()
+    oex, oey = oracle.velocity_table()
+    assert ex == oex.tolist() and ey == oey.tolist()
+    assert np.array_equal(np.array(lbm.weights()), oracle.weights())
+    assert lbm.scale_c() == oracle.scale_c()
+
+
+def test_host_side_validation():
+    L = lbm.lib()
+    good = lbm.make_params(64, 48, 0.7)
+    n = lbm.workspace_bytes(good)
+    assert n > 37 * 2 * 64 * 48 * 8
+    for bad in (lbm.make_params(6, 48, 0.7), lbm.make_params(64, 6, 0.7), lbm.make_params(64, 48, 0.5),
+                lbm.make_params(64, 48, float("nan"))):
+        assert lbm.workspace_bytes(bad) == 0
+    p = lbm.make_params(64, 48, 0.7)
+    p.precision = 7
+    assert lbm.workspace_bytes(p) == 0
+    h = ctypes.c_void_p()
+    assert L.lbm_create(ctypes.byref(lbm.make_params(64, 48, 0.4)), ctypes.c_void_p(4096), 1 << 30,
+                        None, ctypes.byref(h)) == 1
+    assert b"invalid" in L.lbm_last_error(None)
+    assert L.lbm_create(ctypes.byref(good), ctypes.c_void_p(4096), n - 1, None, ctypes.byref(h)) == 2
+    assert L.lbm_create(ctypes.byref(good), ctypes.c_void_p(4096 + 8), n, None, ctypes.byref(h)) == 1
+    assert not h.value
+    # FP32 storage halves the population buffers; the adjoint adds FP64 lambda
+    p32 = lbm.make_params(64, 48, 0.7, precision="fp32")
+    assert lbm.workspace_bytes(p32) < n
+    assert lbm.workspace_bytes(lbm.make_params(64, 48, 0.7, adjoint=True)) > n
+
+
+def test_python_binding_refuses_missing_library(monkeypatch):
+    monkeypatch.setattr(lbm, "_lib", None)
+    monkeypatch.setattr(lbm, "LIB_PATH", "/nonexistent/liblbm.so")
+    with pytest.raises(lbm.LBMError):
+        lbm.lib()

@@ -1,0 +1,253 @@
+"""GPU parity of the forward step (propagate, bc, collide, step) against the
+CPU oracle, through the C ABI.
+
+Bars: propagate is a permutation, so bitwise; everything with arithmetic is
+compared per population relative to its weight, max |f_gpu - f_ref| / w_l,
+against 1e-12 (FP64).  FP32-shifted storage is compared per field against
+the FP64 oracle with a bound derived from FP32 rounding.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1703_04594_amd import inputs
+from paper_1703_04594_amd.lbm import Lattice, RtProfile
+
+from _util import G, TAU, TB, TT, W, WC, oracle_rt, oracle_window_site, rt_fields, say
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def tg(a, dtype=torch.float64):
+    return torch.tensor(np.ascontiguousarray(a), dtype=dtype, device=DEV)
+
+
+def relw(a, b):
+    return float(np.max(np.abs(np.asarray(a, dtype=np.float64) - b) / WC))
+
+
+def tagged(lx, ly):
+    return (np.arange(37 * lx * ly, dtype=np.float64) + 1.0).reshape(37, lx, ly)
+
+
+MODES = [("split", "wrap"), ("split", "halo"), ("fused", "wrap"), ("fused", "halo")]
+
+
+@pytest.mark.parametrize("lx,ly", [(7, 7), (37, 45), (64, 129), (300, 1030)])
+@pytest.mark.parametrize("xmode", ["wrap", "halo"])
+@pytest.mark.parametrize("ybc", ["periodic", "walls"])
+def test_propagate_is_the_bitwise_permutation(lx, ly, xmode, ybc):
+    say(f"propagate permutation {lx}x{ly} {xmode} {ybc}")
+    t = tagged(lx, ly)
+    lat = Lattice(lx, ly, TAU, ybc=ybc, xmode=xmode, device=DEV)
+    lat.set_pops(tg(t))
+    lat.propagate()
+    got = lat.get_pops().cpu().numpy()
+    ref = oracle.RefLattice(lx, ly, TAU, ybc=oracle.PERIODIC if ybc == "periodic" else oracle.WALL)
+    ref.set_pops(t)
+    ref.propagate()
+    want = ref.get_pops()
+    ok = ~np.isnan(want)
+    assert np.array_equal(got[ok], want[ok])
+
+
+@pytest.mark.parametrize("lx,ly", [(37, 45), (256, 130)])
+def test_propagate_fp32_is_bitwise(lx, ly):
+    say(f"propagate fp32 {lx}x{ly}")
+    t = tagged(lx, ly)
+    assert t.max() < 2 ** 24
+    lat = Lattice(lx, ly, TAU, precision="fp32", ybc="periodic", device=DEV)
+    lat.set_pops(tg(t, torch.float32))
+    lat.propagate()
+    ref = oracle.RefLattice(lx, ly, TAU, ybc=oracle.PERIODIC)
+    ref.set_pops(t)
+    ref.propagate()
+    assert np.array_equal(lat.get_pops().cpu().numpy().astype(np.float64), ref.get_pops())
+
+
+def random_state(lx, ly, seed, amp=0.05):
+    return WC * (1.0 + amp * inputs.population_noise(lx, ly, seed))
+
+
+@pytest.mark.parametrize("g", [0.0, -1e-3])
+def test_collide_matches_oracle(g):
+    lx, ly = 45, 77
+    say(f"collide {lx}x{ly} g={g}")
+    f0 = random_state(lx, ly, 3)
+    lat = Lattice(lx, ly, TAU, g, ybc="periodic", device=DEV)
+    lat.set_pops(tg(f0))
+    lat.collide()
+    ref = oracle.RefLattice(lx, ly, TAU, g, ybc=oracle.PERIODIC)
+    ref.set_pops(f0)
+    ref.collide()
+    err = relw(lat.get_pops().cpu().numpy(), ref.get_pops())
+    assert err <= 1e-13, (err)
+
+
+def test_bc_matches_oracle():
+    lx, ly = 33, 20
+    say("bc")
+    f0 = random_state(lx, ly, 4)
+    lat = Lattice(lx, ly, TAU, 0.0, TB, TT, device=DEV)
+    lat.set_pops(tg(f0))
+    with pytest.raises(Exception):
+        lat.bc()                     # no propagate since the state was set
+    lat.propagate()
+    lat.bc()
+    ref = oracle.RefLattice(lx, ly, TAU, 0.0, TB, TT)
+    ref.set_pops(f0)
+    ref.propagate()
+    ref.bc()
+    # wall slots: E^w_l rho_m with E^w from two different evaluation orders
+    err = relw(lat.get_pops().cpu().numpy(), ref.get_pops())
+    assert err <= 1e-14, err
+
+
+@pytest.mark.parametrize("step,xmode", MODES)
+def test_rt_run_256x128_matches_oracle(step, xmode):
+    """The small Rayleigh-Taylor case: 256x128, walls, 50 steps, every 10."""
+    lx, ly = 256, 128
+    say(f"RT 256x128 {step} {xmode}")
+    P = inputs.rt_perturbation(lx, ly, 1)
+    lat = Lattice(lx, ly, TAU, G, TB, TT, step=step, xmode=xmode, device=DEV)
+    lat.init_rt(tg(P))
+    ref, _ = oracle_rt(lx, ly, 1, 0)
+    err = relw(lat.get_pops().cpu().numpy(), ref.get_pops())
+    assert err <= 1e-14, (err)
+    for k in range(5):
+        lat.step(10)
+        ref.step(10)
+        err = relw(lat.get_pops().cpu().numpy(), ref.get_pops())
+        assert err <= 1e-12, (err, k)
+    rho, ux, uy, T = (t.cpu().numpy() for t in lat.macros())
+    r_rho, r_ux, r_uy, r_T = ref.macros()
+    assert np.max(np.abs(rho - r_rho) / r_rho) <= 1e-12
+    assert np.max(np.abs(T - r_T) / r_T) <= 1e-12
+    assert np.max(np.abs(ux - r_ux)) <= 1e-12 and np.max(np.abs(uy - r_uy)) <= 1e-12
+
+
+@pytest.mark.parametrize("step", ["split", "fused"])
+@pytest.mark.parametrize("lx,ly,ybc", [(7, 7, "walls"), (37, 45, "periodic"), (37, 45, "walls"), (70, 300, "walls")])
+def test_ragged_lattices(step, lx, ly, ybc):
+    say(f"ragged {lx}x{ly} {ybc} {step}")
+    f0 = random_state(lx, ly, 8, amp=0.03)
+    g = -1e-4
+    lat = Lattice(lx, ly, TAU, g, TB, TT, ybc=ybc, step=step, device=DEV)
+    lat.set_pops(tg(f0))
+    lat.step(20)
+    ref = oracle.RefLattice(lx, ly, TAU, g, TB, TT, ybc=oracle.PERIODIC if ybc == "periodic" else oracle.WALL)
+    ref.set_pops(f0)
+    ref.step(20)
+    err = relw(lat.get_pops().cpu().numpy(), ref.get_pops())
+    assert err <= 1e-12, (err)
+
+
+def test_split_calls_equal_step():
+    lx, ly = 50, 40
+    f0 = random_state(lx, ly, 9)
+    a = Lattice(lx, ly, TAU, G, TB, TT, device=DEV)
+    b = Lattice(lx, ly, TAU, G, TB, TT, device=DEV)
+    a.set_pops(tg(f0))
+    b.set_pops(tg(f0))
+    for _ in range(3):
+        a.propagate()
+        a.bc()
+        a.collide()
+    b.step(3)
+    assert torch.equal(a.get_pops(), b.get_pops())
+
+
+def test_macros_conservation_and_roundtrips():
+    lx, ly = 64, 48
+    f0 = random_state(lx, ly, 10)
+    lat = Lattice(lx, ly, TAU, ybc="periodic", device=DEV)
+    lat.set_pops(tg(f0))
+    assert torch.equal(lat.get_pops(), tg(f0))
+    ref = oracle.RefLattice(lx, ly, TAU, ybc=oracle.PERIODIC)
+    ref.set_pops(f0)
+    for a, b in zip(lat.macros(), ref.macros()):
+        assert np.max(np.abs(a.cpu().numpy() - b)) <= 1e-14 * max(1.0, np.abs(b).max())
+    c0 = lat.conservation().cpu().numpy()
+    # different summation orders (the oracle sums ~1e5 terms serially, typical
+    # error sqrt(n) eps sum|x|): bound by the sum of the magnitudes summed
+    ex, ey = oracle.velocity_table()
+    c = oracle.scale_c()
+    xx, yy = (c * ex)[:, None, None], (c * ey)[:, None, None]
+    mag = np.array([np.abs(f0).sum(), np.abs(xx * f0).sum(), np.abs(yy * f0).sum(),
+                    ((xx * xx + yy * yy) * np.abs(f0)).sum()])
+    assert np.all(np.abs(c0 - ref.conservation()) <= 1e-12 * mag)
+    lat.step(25)
+    c1 = lat.conservation().cpu().numpy()
+    # periodic, no gravity: collision invariants are conserved by the step
+    assert np.all(np.abs(c1 - c0) <= 1e-12 * mag)
+    # bitwise reproducible reductions and state snapshots
+    assert torch.equal(lat.conservation(), lat.conservation())
+    s = lat.get_state()
+    lat.step(3)
+    f3 = lat.get_pops()
+    lat.set_state(s)
+    lat.step(3)
+    assert torch.equal(lat.get_pops(), f3)
+
+
+def test_uniform_rest_state_at_wall_temperature_stays():
+    lat = Lattice(32, 24, TAU, 0.0, 0.9, 0.9, step="fused", device=DEV)
+    ones = torch.ones((32, 24), dtype=torch.float64, device=DEV)
+    z = torch.zeros_like(ones)
+    lat.init(1.2 * ones, z, z, 0.9 * ones)
+    f0 = lat.get_pops().cpu().numpy()
+    lat.step(40)
+    err = relw(lat.get_pops().cpu().numpy(), f0)
+    assert err <= 40 * 1e-14, (err)
+
+
+@pytest.mark.parametrize("step", ["split", "fused"])
+def test_fp32_shifted_against_fp64_oracle(step):
+    """FP32 deviations: per-field error after 50 steps of the 256x128 RT run.
+    FP32 rounding of deviations O(0.3 w) is ~2e-8 of rho per step; the bound
+    below leaves an order of magnitude over 50 steps."""
+    lx, ly = 256, 128
+    say(f"fp32 RT {step}")
+    P = inputs.rt_perturbation(lx, ly, 1)
+    lat = Lattice(lx, ly, TAU, G, TB, TT, precision="fp32", step=step, device=DEV)
+    lat.init_rt(tg(P))
+    lat.step(50)
+    ref, _ = oracle_rt(lx, ly, 1, 50)
+    rho, ux, uy, T = (t.cpu().numpy() for t in lat.macros())
+    r_rho, r_ux, r_uy, r_T = ref.macros()
+    e_rho = np.max(np.abs(rho - r_rho) / r_rho)
+    e_T = np.max(np.abs(T - r_T) / r_T)
+    e_u = max(np.max(np.abs(ux - r_ux)), np.max(np.abs(uy - r_uy)))
+    say(f"fp32 errors rho {e_rho:.2e} T {e_T:.2e} u {e_u:.2e}")
+    assert e_rho <= 1e-5 and e_T <= 1e-5 and e_u <= 1e-5
+
+
+def test_fp32_init_and_macros_are_fp64_exact_at_rest():
+    # rest state at unit temperature: deviations are exactly zero
+    lat = Lattice(16, 16, TAU, precision="fp32", ybc="periodic", device=DEV)
+    ones = torch.ones((16, 16), dtype=torch.float64, device=DEV)
+    lat.init(ones, 0 * ones, 0 * ones, ones)
+    assert torch.count_nonzero(lat.get_pops()) == 0
+    rho, ux, uy, T = lat.macros()
+    assert torch.equal(rho, ones) and torch.equal(T, ones)
+
+
+@pytest.mark.parametrize("step", ["split", "fused"])
+def test_full_size_2048x4096_sampled_parity(step):
+    """At the full 2048x4096 size and the benchmark's launch configuration:
+    50 FP64 steps, then sampled sites against windowed oracle runs."""
+    lx, ly, n = 2048, 4096, 50
+    say(f"full-size sampled parity {step}")
+    P = inputs.rt_perturbation(lx, ly, 1)
+    lat = Lattice(lx, ly, TAU, G, TB, TT, step=step, device=DEV)
+    lat.init_rt(tg(P))
+    lat.step(n)
+    f = lat.get_pops()
+    for (x0, y0) in [(0, 0), (2047, 4095), (1, 2), (1000, 2047), (1500, 2048), (5, 4093), (2046, 150)]:
+        got = f[:, x0, y0].cpu().numpy()
+        want = oracle_window_site(P, lx, ly, x0, y0, n)
+        err = float(np.max(np.abs(got - want) / W))
+        say(f"  site ({x0},{y0}) err {err:.2e}")
+        assert err <= 1e-12, (x0, y0, err)
