@@ -147,6 +147,112 @@ def run(args):
     return res
 
 
+def fp32_accuracy(args, nsteps=5000, every=500):
+    """FP32-shifted vs FP64 on the bench lattice: per-field relative errors
+    every `every` steps.  The FP64 reference is the GPU FP64 path (itself
+    pinned to the oracle by the parity tests).  rho and T errors are given
+    relative to the field's spread, ||q32 - q64|| / ||q64 - mean(q64)||, and
+    to its size, ||q32 - q64|| / ||q64||; u relative to max(||u64||,
+    1e-6 sqrt(S))."""
+    import torch
+
+    from paper_1703_04594_amd import inputs
+    from paper_1703_04594_amd.lbm import Lattice
+
+    lx, ly, dev = args.lx, args.ly, "cuda:0"
+    P = torch.tensor(inputs.rt_perturbation(lx, ly, 1), device=dev)
+    lats = {}
+    for prec in ("fp64", "fp32"):
+        lats[prec] = Lattice(lx, ly, 0.7, -1e-5, 4 / 3, 2 / 3, precision=prec, step="fused", device=dev)
+        lats[prec].init_rt(P)
+    rows = []
+    floor_u = 1e-6 * (lx * ly) ** 0.5
+    for k in range(nsteps // every):
+        for lat in lats.values():
+            lat.step(every)
+        a = lats["fp64"].macros()
+        b = lats["fp32"].macros()
+        rho64, T64 = a[0], a[3]
+        u64 = torch.stack([a[1], a[2]])
+        u32 = torch.stack([b[1], b[2]])
+        row = {"step": (k + 1) * every}
+        for name, x64, x32 in (("rho", rho64, b[0]), ("T", T64, b[3])):
+            d = float((x32 - x64).norm())
+            row[name + "_vs_spread"] = d / float((x64 - x64.mean()).norm())
+            row[name + "_vs_size"] = d / float(x64.norm())
+        row["u"] = float((u32 - u64).norm()) / max(float(u64.norm()), floor_u)
+        rows.append({k2: (round(v, 9) if isinstance(v, float) else v) for k2, v in row.items()})
+        log(f"bench: fp32 accuracy {row}")
+    del lats
+    torch.cuda.empty_cache()
+    return rows
+
+
+def adjoint_at_scale(lx=1024, ly=2048, nsteps=10000, budget=32 << 30):
+    """Gradient of 1/2 sum (T_N - T*)^2 w.r.t. the initial perturbation field
+    P and tau on the 1024x2048 lattice, FP32 forward states, FP64 adjoint,
+    binomial checkpointing with all stored states inside `budget` bytes."""
+    import torch
+
+    from paper_1703_04594_amd import inputs
+    from paper_1703_04594_amd.autograd import RolloutConfig, rt_temperature
+    from paper_1703_04594_amd.lbm import Lattice
+
+    dev = "cuda:0"
+    P = torch.tensor(inputs.rt_perturbation(lx, ly, 1), device=dev)
+    P2 = torch.tensor(inputs.rt_perturbation(lx, ly, 2), device=dev)
+    lat = Lattice(lx, ly, 0.7, -1e-5, 4 / 3, 2 / 3, precision="fp32", step="fused", device=dev)
+    lat.init_rt(P2)
+    lat.step(nsteps)
+    Tt = lat.macros()[3].clone()
+    # plain forward wall time, and per-step kernel times
+    lat.init_rt(P)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat.step(nsteps)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    del lat
+    probe = Lattice(lx, ly, 0.7, -1e-5, 4 / 3, 2 / 3, precision="fp32", step="fused", adjoint=True, device=dev)
+    probe.init_rt(P)
+    ws_bytes = probe.workspace.numel()
+    st = probe.get_state()
+    probe.step(1)
+    probe.seed_temperature(torch.ones((lx, ly), dtype=torch.float64, device=dev))
+    dacc = torch.zeros((), dtype=torch.float64, device=dev)
+    t_adj = time_launches(lambda: probe.adjoint_step(st, dacc), probe.stream, 20)
+    t_step = time_launches(lambda: probe.step(1), probe.stream, 20)
+    state_bytes = probe.state_bytes
+    del probe, st
+    torch.cuda.empty_cache()
+    # full gradient: forward with checkpoints + reverse sweep
+    cfg = RolloutConfig(lx, ly, nsteps, precision="fp32", checkpoint="binomial",
+                        memory_budget=budget - ws_bytes)
+    torch.cuda.reset_peak_memory_stats()
+    base_mem = torch.cuda.memory_allocated()
+    Pg = P.clone().requires_grad_(True)
+    tg = torch.tensor(0.7, dtype=torch.float64, device=dev, requires_grad=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    T = rt_temperature(Pg, tg, cfg)
+    loss = 0.5 * ((T - Tt) ** 2).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    t_grad = time.perf_counter() - t0
+    peak = torch.cuda.max_memory_allocated() - base_mem
+    out = {"lattice": f"{lx}x{ly}", "steps": nsteps, "checkpoint": "binomial",
+           "budget_GB": round(budget / 2 ** 30, 1), "state_MB": round(state_bytes / 2 ** 20, 1),
+           "snapshot_slots": cfg.stats.get("slots"), "forward_steps_total": cfg.stats.get("forward_steps"),
+           "adjoint_step_ms": round(t_adj * 1e3, 4), "forward_step_ms": round(t_step * 1e3, 4),
+           "adjoint_over_forward_step": round(t_adj / t_step, 3),
+           "forward_wall_s": round(t_fwd, 3), "gradient_wall_s": round(t_grad, 3),
+           "gradient_over_forward_wall": round(t_grad / t_fwd, 3),
+           "peak_memory_GB": round(peak / 2 ** 30, 2), "loss": float(loss),
+           "dL_dtau": float(tg.grad), "dL_dP_norm": float(Pg.grad.norm())}
+    log(f"bench: adjoint at scale {out}")
+    return out
+
+
 def cpu_baseline(args, budget_s=15.0):
     """The oracle (OpenMP build of the plain C source) on the host cores, on a
     bounded number of steps of the same lattice."""
@@ -173,6 +279,47 @@ def cpu_baseline(args, budget_s=15.0):
             "kind": "oracle", "sample": f"{n} FP64 steps of the {lx}x{ly} RT lattice after 1 untimed step"}
 
 
+def profile_workload(args):
+    """Short fixed sequence for rocprofv3 runs: a plain device copy of known
+    size (calibrates the HBM byte counters), then FP64 and FP32 fused steps,
+    the FP64 split kernels and FP32 adjoint steps on the bench lattice."""
+    import torch
+
+    from paper_1703_04594_amd import inputs
+    from paper_1703_04594_amd.lbm import Lattice
+
+    lx, ly, dev = args.lx, args.ly, "cuda:0"
+    n = 1 << 30
+    a = torch.empty(n, dtype=torch.uint8, device=dev).fill_(1)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)                     # 1 GiB read + 1 GiB written per dispatch
+    torch.cuda.synchronize()
+    del a, b
+    P = torch.tensor(inputs.rt_perturbation(lx, ly, 1), device=dev)
+    for prec in ("fp64", "fp32"):
+        lat = Lattice(lx, ly, 0.7, -1e-5, 4 / 3, 2 / 3, precision=prec, step="fused", device=dev)
+        lat.init_rt(P)
+        lat.step(args.steps)
+        torch.cuda.synchronize()
+        del lat
+    lat = Lattice(lx, ly, 0.7, -1e-5, 4 / 3, 2 / 3, precision="fp64", step="split", device=dev)
+    lat.init_rt(P)
+    lat.step(args.steps)
+    torch.cuda.synchronize()
+    del lat
+    lat = Lattice(lx, ly, 0.7, -1e-5, 4 / 3, 2 / 3, precision="fp32", step="fused", adjoint=True, device=dev)
+    lat.init_rt(P)
+    st = lat.get_state()
+    lat.step(1)
+    lat.seed_temperature(torch.ones((lx, ly), dtype=torch.float64, device=dev))
+    dacc = torch.zeros((), dtype=torch.float64, device=dev)
+    for _ in range(args.steps):
+        lat.adjoint_step(st, dacc)
+    torch.cuda.synchronize()
+    print(json.dumps({"profile_workload": "done", "steps": args.steps}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -181,12 +328,22 @@ def main():
     ap.add_argument("--lx", type=int, default=2048)
     ap.add_argument("--ly", type=int, default=4096)
     ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--skip-reports", action="store_true",
+                    help="skip the FP32 accuracy and adjoint-at-scale measurements")
+    ap.add_argument("--profile", action="store_true",
+                    help="run the short fixed kernel sequence used under rocprofv3")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only; multi-GPU X-slab sharding is not implemented",
               file=sys.stderr)
         sys.exit(2)
+    if args.profile:
+        profile_workload(args)
+        return
     res = run(args)
+    if not args.skip_reports:
+        res["fp32_accuracy_5000_steps"] = fp32_accuracy(args)
+        res["adjoint_1024x2048_10000_steps"] = adjoint_at_scale()
     res["cpu_baseline"] = None if args.skip_cpu else cpu_baseline(args)
     print(json.dumps(res), flush=True)
 

@@ -27,67 +27,88 @@ namespace lbm {
 
 struct AdjArgs { double tau, omega, gy; };
 
-// mu <- collide^T lambda at one site, in place; returns the site's d/dtau term.
-__device__ __forceinline__ double adjoint_site(const double (&gv)[NPOP], double (&lam)[NPOP], const AdjArgs& a)
+// Per-site scalars of collide^T that depend only on the gathered moments.
+struct AdjSite {
+    double rho, inv, ux, uy, uys, E, th, u2, cux, cuy;
+};
+
+__device__ __forceinline__ AdjSite adj_site_scalars(double m0, double sx, double sy, double s2, const AdjArgs& a)
+{
+    AdjSite q;
+    q.rho = m0;
+    q.inv = 1.0 / m0;
+    q.ux = C * sx * q.inv;
+    q.uy = C * sy * q.inv;
+    q.E = C2 * s2;
+    const double T = 0.5 * (q.E * q.inv - (q.ux * q.ux + q.uy * q.uy));
+    q.uys = q.uy + a.tau * a.gy;
+    q.th = T - 1.0 + a.tau * (1.0 - a.tau) * a.gy * a.gy * 0.5;
+    q.u2 = q.ux * q.ux + q.uys * q.uys;
+    q.cux = C * q.ux;
+    q.cuy = C * q.uys;
+    return q;
+}
+
+// mu <- collide^T lambda at one site, in place, given the gathered moments
+// (m0, sx, sy, s2) and Lg = sum_l lambda_l g_l; returns the site's d/dtau term.
+// The shell coefficients of the equilibrium and their derivatives are formed
+// shell by shell (populations are ordered by shell), so only one shell's worth
+// is live at a time.
+__device__ __forceinline__ double adjoint_site(double m0, double sx, double sy, double s2, double Lg,
+                                               double (&lam)[NPOP], const AdjArgs& a)
 {
     using K = ShellK<double>;
-    double m0, sx, sy, s2;
-    hop_moments<double>(gv, m0, sx, sy, s2);
-    const double rho = m0, inv = 1.0 / rho;
-    const double ux = C * sx * inv, uy = C * sy * inv;
-    const double E = C2 * s2;
-    const double T = 0.5 * (E * inv - (ux * ux + uy * uy));
-    const double uys = uy + a.tau * a.gy;
-    const double th = T - 1.0 + a.tau * (1.0 - a.tau) * a.gy * a.gy * 0.5;
-    const double u2 = ux * ux + uys * uys;
-    const double cux = C * ux, cuy = C * uys;
-    double A0m1[NSHELL], A1[NSHELL], A2[NSHELL], dA0du2[NSHELL], dA0dth[NSHELL];
+    const AdjSite q = adj_site_scalars(m0, sx, sy, s2, a);
+    double SP = 0.0, Sax = 0.0, Say = 0.0, Su2 = 0.0, Sth = 0.0;
 #pragma unroll
     for (int s = 0; s < NSHELL; ++s) {
-        A0m1[s] = u2 * (-0.5 + 0.125 * u2) + th * (K::k1(s) + u2 * K::k2(s) + th * K::k3(s));
-        A1[s] = 1.0 - 0.5 * u2 + th * K::k4(s);
-        A2[s] = 0.5 - 0.25 * u2 + th * K::k5(s);
-        dA0du2[s] = -0.5 + 0.25 * u2 + th * K::k2(s);
-        dA0dth[s] = K::k1(s) + u2 * K::k2(s) + 2.0 * th * K::k3(s);
-    }
-    double SP = 0.0, Sax = 0.0, Say = 0.0, Su2 = 0.0, Sth = 0.0, D = 0.0;
+        const double A0m1 = q.u2 * (-0.5 + 0.125 * q.u2) + q.th * (K::k1(s) + q.u2 * K::k2(s) + q.th * K::k3(s));
+        const double A1 = 1.0 - 0.5 * q.u2 + q.th * K::k4(s);
+        const double A2 = 0.5 - 0.25 * q.u2 + q.th * K::k5(s);
+        const double dA0du2 = -0.5 + 0.25 * q.u2 + q.th * K::k2(s);
+        const double dA0dth = K::k1(s) + q.u2 * K::k2(s) + 2.0 * q.th * K::k3(s);
+        double sP = 0.0, sax = 0.0, say = 0.0, su2 = 0.0, sth = 0.0;
 #pragma unroll
-    for (int l = 0; l < NPOP; ++l) {
-        const int s = SHELL[l];
-        double P, dPdu2, dPdth;
-        const double lw = lam[l] * W_SHELL[s];
-        if (l == 0) {
-            P = 1.0 + A0m1[0];
-            dPdu2 = dA0du2[0];
-            dPdth = dA0dth[0];
-        } else {
-            const double av = hop_dot<double>(l, cux, cuy);
+        for (int l = 0; l < NPOP; ++l) {
+            if (SHELL[l] != s) continue;
+            if (l == 0) {
+                sP += lam[0] * (1.0 + A0m1);
+                su2 += lam[0] * dA0du2;
+                sth += lam[0] * dA0dth;
+                continue;
+            }
+            const double av = hop_dot<double>(l, q.cux, q.cuy);
             double t = av * (1.0 / 24.0) + 1.0 / 6.0;
-            t = t * av + A2[s];
-            t = t * av + A1[s];
-            P = 1.0 + (t * av + A0m1[s]);
-            const double dPda = A1[s] + av * (2.0 * A2[s] + av * (0.5 + av * (1.0 / 6.0)));
-            dPdu2 = dA0du2[s] + av * (-0.5 - 0.25 * av);
-            dPdth = dA0dth[s] + av * (K::k4(s) + av * K::k5(s));
-            const double Z = lw * dPda;
-            if (EX[l] != 0) Sax += (double)EX[l] * Z;
-            if (EY[l] != 0) Say += (double)EY[l] * Z;
+            t = t * av + A2;
+            t = t * av + A1;
+            const double P = 1.0 + (t * av + A0m1);
+            const double dPda = A1 + av * (2.0 * A2 + av * (0.5 + av * (1.0 / 6.0)));
+            const double Z = lam[l] * dPda;
+            sP += lam[l] * P;
+            if (EX[l] != 0) sax += (double)EX[l] * Z;
+            if (EY[l] != 0) say += (double)EY[l] * Z;
+            su2 += lam[l] * (dA0du2 + av * (-0.5 - 0.25 * av));
+            sth += lam[l] * (dA0dth + av * (K::k4(s) + av * K::k5(s)));
         }
-        SP += lw * P;
-        Su2 += lw * dPdu2;
-        Sth += lw * dPdth;
-        D += lam[l] * (W_SHELL[s] * rho * P - gv[l]);
+        const double ws = W_SHELL[s];
+        SP += ws * sP;
+        Sax += ws * sax;
+        Say += ws * say;
+        Su2 += ws * su2;
+        Sth += ws * sth;
     }
     const double om = a.omega;
-    const double bux = om * rho * (C * Sax + 2.0 * ux * Su2);
-    const double buy = om * rho * (C * Say + 2.0 * uys * Su2);
-    const double bth = om * rho * Sth;
+    const double bux = om * q.rho * (C * Sax + 2.0 * q.ux * Su2);
+    const double buy = om * q.rho * (C * Say + 2.0 * q.uys * Su2);
+    const double bth = om * q.rho * Sth;
     const double bP = om * SP;
+    // sum_l lambda_l (f^eq_l - g_l) = rho SP - Lg
+    const double D = q.rho * SP - Lg;
     const double dtau = -om * om * D + buy * a.gy + bth * (1.0 - 2.0 * a.tau) * a.gy * a.gy * 0.5;
-    const double buxt = bux - bth * ux, buyt = buy - bth * uy;
-    const double bE = 0.5 * bth * inv;
-    const double bjx = buxt * inv, bjy = buyt * inv;
-    const double brho = bP - (buxt * ux + buyt * uy) * inv - 0.5 * bth * E * inv * inv;
+    const double buxt = bux - bth * q.ux, buyt = buy - bth * q.uy;
+    const double bE = 0.5 * bth * q.inv;
+    const double bjx = buxt * q.inv, bjy = buyt * q.inv;
+    const double brho = bP - (buxt * q.ux + buyt * q.uy) * q.inv - 0.5 * bth * q.E * q.inv * q.inv;
     const double cjx = C * bjx, cjy = C * bjy, c2E = C2 * bE;
 #pragma unroll
     for (int l = 0; l < NPOP; ++l) {
@@ -116,45 +137,80 @@ __global__ __launch_bounds__(SITE_THREADS) void k_adj_collide_push(
     const int y = blockIdx.x * SITE_THREADS + threadIdx.x;
     double dtau = 0.0;
     if (y < g.ly) {
-        double gv[NPOP], lam[NPOP];
+        using Cc = typename Store<S>::C;
+        const unsigned yb = (unsigned)y * (unsigned)sizeof(S);
+        const unsigned yd = (unsigned)y * 8u;
+        // lambda_{n+1} at this site and the raw gather of f_n (storage
+        // precision; all loads unconditional -- wall slots read ghost rows and
+        // are replaced below)
+        double lam[NPOP];
+        const double* lcol = lam_in + lg.origin + (long long)x * lg.lyp;
+#pragma unroll
+        for (int l = 0; l < NPOP; ++l) lam[l] = ld_at(lcol + (size_t)l * lg.plane, yd);
+        Cc gl[NPOP];
 #pragma unroll
         for (int l = 0; l < NPOP; ++l) {
-            const int xs = wrap_x(x - EX[l], g.lx);
-            int ys = y - EY[l];
-            if (!WALLS) ys = ys < 0 ? ys + g.ly : (ys >= g.ly ? ys - g.ly : ys);
-            double v = (double)fn[(size_t)l * g.plane + g.origin + (long long)xs * g.lyp + ys];
-            if (Store<S>::shifted) v += wt.w[l];
-            gv[l] = v;
+            int xs = wrap_x(x - EX[l], g.lx);
+            if (WALLS) {
+                gl[l] = (Cc)ld_at(fn + (size_t)l * g.plane + g.origin + (long long)xs * g.lyp - EY[l], yb);
+            } else {
+                int ys = y - EY[l];
+                ys = ys < 0 ? ys + g.ly : (ys >= g.ly ? ys - g.ly : ys);
+                gl[l] = (Cc)fn[(size_t)l * g.plane + g.origin + (long long)xs * g.lyp + ys];
+            }
         }
+        // raw moments of g and Lg = sum_l lambda_l g_l, in FP64
+        double m0 = 0.0, sx = 0.0, sy = 0.0, s2 = 0.0, Lg = 0.0;
         if (WALLS && (y < 3 || y >= g.ly - 3)) {
 #pragma unroll
             for (int l = 0; l < NPOP; ++l) {
-                if (EY[l] == 0) continue;
-                const int wall = EY[l] > 0 ? 0 : 1;
-                const int r = wall == 0 ? y : g.ly - 1 - y;
-                const int en = wall == 0 ? EY[l] : -EY[l];
-                if (en > r) {
-                    const int xs = wrap_x(x - EX[l], g.lx);
-                    gv[l] = wt.ew[wall][l] * wall_rho[(wall * 3 + (en - r - 1)) * g.lx + xs];
+                double v = (double)gl[l];
+                if (Store<S>::shifted) v += W_SHELL[SHELL[l]];
+                if (EY[l] != 0) {
+                    const int wall = EY[l] > 0 ? 0 : 1;
+                    const int r = wall == 0 ? y : g.ly - 1 - y;
+                    const int en = wall == 0 ? EY[l] : -EY[l];
+                    if (en > r) v = wt.ew[wall][l] * wall_rho[(wall * 3 + (en - r - 1)) * g.lx + wrap_x(x - EX[l], g.lx)];
                 }
+                m0 += v;
+                if (EX[l] != 0) sx += (double)EX[l] * v;
+                if (EY[l] != 0) sy += (double)EY[l] * v;
+                if (R2_OF(l) != 0) s2 += (double)R2_OF(l) * v;
+                Lg += lam[l] * v;
+            }
+        } else {
+#pragma unroll
+            for (int l = 0; l < NPOP; ++l) {
+                double v = (double)gl[l];
+                if (Store<S>::shifted) v += W_SHELL[SHELL[l]];
+                m0 += v;
+                if (EX[l] != 0) sx += (double)EX[l] * v;
+                if (EY[l] != 0) sy += (double)EY[l] * v;
+                if (R2_OF(l) != 0) s2 += (double)R2_OF(l) * v;
+                Lg += lam[l] * v;
             }
         }
-        const double* lp = lam_in + lg.origin + (long long)x * lg.lyp + y;
-#pragma unroll
-        for (int l = 0; l < NPOP; ++l) lam[l] = lp[(size_t)l * lg.plane];
-        dtau = adjoint_site(gv, lam, a);
+        dtau = adjoint_site(m0, sx, sy, s2, Lg, lam, a);
+        // propagate^T: push mu_l to (x - ex, y - ey); beyond a wall it lands
+        // in the ghost rows (read by k_adj_bc_fix)
 #pragma unroll
         for (int l = 0; l < NPOP; ++l) {
             const int xd = wrap_x(x - EX[l], g.lx);
-            int yd = y - EY[l];
-            if (!WALLS) yd = yd < 0 ? yd + g.ly : (yd >= g.ly ? yd - g.ly : yd);
-            lam_out[(size_t)l * lg.plane + lg.origin + (long long)xd * lg.lyp + yd] = lam[l];
+            if (WALLS) {
+                st_at(lam_out + (size_t)l * lg.plane + lg.origin + (long long)xd * lg.lyp - EY[l], yd, lam[l]);
+            } else {
+                int ys = y - EY[l];
+                ys = ys < 0 ? ys + g.ly : (ys >= g.ly ? ys - g.ly : ys);
+                lam_out[(size_t)l * lg.plane + lg.origin + (long long)xd * lg.lyp + ys] = lam[l];
+            }
         }
     }
     block_sum1(dtau, partials);
 }
 
 // bc^T and the zeroing of slots nobody pushes to: thread per (wall, row, x).
+// All loads are issued before any store (the ghost rows read for beta and
+// the interior row written never overlap).
 __global__ __launch_bounds__(256) void k_adj_bc_fix(double* __restrict__ lam, Geo lg, WallTable wt)
 {
     const int t = blockIdx.x * 256 + threadIdx.x;
@@ -164,19 +220,18 @@ __global__ __launch_bounds__(256) void k_adj_bc_fix(double* __restrict__ lam, Ge
     const int y = wall == 0 ? r : lg.ly - 1 - r;
     const int yg = wall == 0 ? -r - 1 : lg.ly + r;
     double* col = lam + lg.origin + (long long)x * lg.lyp;
+    double gh[NPOP], in[NPOP];
+#pragma unroll
+    for (int l = 0; l < NPOP; ++l) {
+        const int en = wall == 0 ? EY[l] : -EY[l];
+        gh[l] = (en >= r + 1) ? col[(size_t)l * lg.plane + yg] : 0.0;
+        in[l] = (-en > r) ? 0.0 : col[(size_t)l * lg.plane + y];
+    }
     double beta = 0.0;
 #pragma unroll
-    for (int l = 0; l < NPOP; ++l) {
-        const int en = wall == 0 ? EY[l] : -EY[l];
-        if (en >= r + 1) beta += wt.ew[wall][l] * col[(size_t)l * lg.plane + yg];
-    }
+    for (int l = 0; l < NPOP; ++l) beta += wt.ew[wall][l] * gh[l];
 #pragma unroll
-    for (int l = 0; l < NPOP; ++l) {
-        const int en = wall == 0 ? EY[l] : -EY[l];
-        double* p = col + (size_t)l * lg.plane + y;
-        const double v = (-en > r) ? 0.0 : *p;
-        *p = v + beta;
-    }
+    for (int l = 0; l < NPOP; ++l) col[(size_t)l * lg.plane + y] = in[l] + beta;
 }
 
 // lambda_l = d(x,y) dT/df_l = d (|xi_l - u|^2 - 2T) / (2 rho), with

@@ -26,7 +26,7 @@ struct Plan {
     size_t elem;      // bytes per stored population value
     size_t state_bytes;
     size_t off_buf[2];
-    size_t off_wall;  // 6 * lx doubles
+    size_t off_wall;  // 2 x 6 * lx doubles (double-buffered wall densities)
     size_t off_part;  // RED_BLOCKS * 4 doubles, then 2 doubles of loss/dtau scratch
     size_t off_lam[2];
     size_t off_apart; // adjoint: one double per collide block
@@ -70,7 +70,7 @@ Plan plan(const lbm_params* p)
     size_t off = 0;
     pl.off_buf[0] = off; off += pl.state_bytes;
     pl.off_buf[1] = off; off += pl.state_bytes;
-    pl.off_wall = off; off += align_up(6 * (size_t)p->lx * 8, ALIGN);
+    pl.off_wall = off; off += 2 * align_up(6 * (size_t)p->lx * 8, ALIGN);
     pl.off_part = off; off += align_up(((size_t)RED_BLOCKS * 4 + 2) * 8, ALIGN);
     if (p->adjoint) {
         const size_t lb = align_up((size_t)NPOP * pl.lgeo.plane * 8, ALIGN);
@@ -96,12 +96,17 @@ struct lbm_ctx {
     bool have_prev;    // the other buffer holds the state before the last propagate
     int lam_cur;
     bool have_lambda;
+    // wall densities (rows 0..2 and ly-3..ly-1) of population buffer wr_buf
+    // (-1: none) live in wall table wr_cur; the other table receives the
+    // densities the next collide or fused step writes
+    int wr_cur;
+    int wr_buf;
     WallTable wt;
     CollideArgs cargs;
     std::string err;
 
     void* buf(int i) { return ws + pl.off_buf[i]; }
-    double* wall_rho() { return reinterpret_cast<double*>(ws + pl.off_wall); }
+    double* wall_rho(int i) { return reinterpret_cast<double*>(ws + pl.off_wall + i * align_up(6 * (size_t)p.lx * 8, ALIGN)); }
     double* partials() { return reinterpret_cast<double*>(ws + pl.off_part); }
     double* scratch2() { return partials() + (size_t)RED_BLOCKS * 4; }
     double* lam(int i) { return reinterpret_cast<double*>(ws + pl.off_lam[i]); }
@@ -176,11 +181,22 @@ lbm_status launch_pre_stream(lbm_ctx* c, S* src)
 }
 
 template <typename S>
-lbm_status launch_wall_density(lbm_ctx* c, const S* src)
+lbm_status launch_wall_density(lbm_ctx* c, const S* src, double* out)
 {
     const Geo& g = c->pl.geo;
-    hipLaunchKernelGGL((k_wall_density<S>), dim3((6 * g.lx + 255) / 256), dim3(256), 0, c->stream, src, g, c->wall_rho());
+    hipLaunchKernelGGL((k_wall_density<S>), dim3((6 * g.lx + 255) / 256), dim3(256), 0, c->stream, src, g, out);
     return check_launch(c, "wall_density");
+}
+
+// Makes wall table wr_cur hold the wall densities of population buffer b.
+template <typename S>
+lbm_status ensure_wall_density(lbm_ctx* c, int b)
+{
+    if (c->wr_buf == b) return LBM_OK;
+    lbm_status s = launch_wall_density<S>(c, (const S*)c->buf(b), c->wall_rho(c->wr_cur));
+    if (s) return s;
+    c->wr_buf = b;
+    return LBM_OK;
 }
 
 template <typename S>
@@ -192,6 +208,7 @@ lbm_status do_propagate(lbm_ctx* c)
     if (s) return s;
     s = launch_propagate<S>(c, src, dst);
     if (s) return s;
+    if (c->wr_buf == 1 - c->cur) c->wr_buf = -1;   // destination overwritten
     c->cur = 1 - c->cur;
     c->have_prev = true;
     return LBM_OK;
@@ -203,10 +220,10 @@ lbm_status do_bc(lbm_ctx* c)
     if (c->p.ybc == LBM_Y_PERIODIC) return LBM_OK;
     if (!c->have_prev) return fail(c, LBM_ERR_STATE, "bc: no propagate since the state was set");
     const Geo& g = c->pl.geo;
-    lbm_status s = launch_wall_density<S>(c, (const S*)c->buf(1 - c->cur));
+    lbm_status s = ensure_wall_density<S>(c, 1 - c->cur);
     if (s) return s;
     hipLaunchKernelGGL((k_bc_apply<S>), dim3((NSLOT * g.lx + 255) / 256), dim3(256), 0, c->stream,
-                       (S*)c->buf(c->cur), g, (const double*)c->wall_rho(), c->wt);
+                       (S*)c->buf(c->cur), g, (const double*)c->wall_rho(c->wr_cur), c->wt);
     return check_launch(c, "bc_apply");
 }
 
@@ -214,7 +231,17 @@ template <typename S>
 lbm_status do_collide(lbm_ctx* c)
 {
     const Geo& g = c->pl.geo;
-    hipLaunchKernelGGL((k_collide<S>), site_grid(g), dim3(SITE_THREADS), 0, c->stream, (S*)c->buf(c->cur), g, c->cargs);
+    if (c->p.ybc == LBM_Y_WALLS) {
+        hipLaunchKernelGGL((k_collide<S, true>), site_grid(g), dim3(SITE_THREADS), 0, c->stream, (S*)c->buf(c->cur), g,
+                           c->cargs, c->wall_rho(1 - c->wr_cur));
+        lbm_status s = check_launch(c, "collide");
+        if (s) return s;
+        c->wr_cur = 1 - c->wr_cur;
+        c->wr_buf = c->cur;
+        return LBM_OK;
+    }
+    hipLaunchKernelGGL((k_collide<S, false>), site_grid(g), dim3(SITE_THREADS), 0, c->stream, (S*)c->buf(c->cur), g,
+                       c->cargs, (double*)nullptr);
     return check_launch(c, "collide");
 }
 
@@ -228,23 +255,28 @@ lbm_status do_step_fused(lbm_ctx* c)
     if (s) return s;
     const bool walls = c->p.ybc == LBM_Y_WALLS;
     if (walls) {
-        s = launch_wall_density<S>(c, src);
+        s = ensure_wall_density<S>(c, c->cur);
         if (s) return s;
     }
     const bool wrap = c->p.xmode == LBM_X_WRAP;
-    const double* wr = c->wall_rho();
+    const double* wr = c->wall_rho(c->wr_cur);
+    double* wo = c->wall_rho(1 - c->wr_cur);
     if (wrap && walls)
-        hipLaunchKernelGGL((k_step_fused<S, true, true>), site_grid(g), dim3(SITE_THREADS), 0, c->stream, src, dst, g, c->cargs, wr, c->wt);
+        hipLaunchKernelGGL((k_step_fused<S, true, true>), site_grid(g), dim3(SITE_THREADS), 0, c->stream, src, dst, g, c->cargs, wr, c->wt, wo);
     else if (wrap)
-        hipLaunchKernelGGL((k_step_fused<S, true, false>), site_grid(g), dim3(SITE_THREADS), 0, c->stream, src, dst, g, c->cargs, wr, c->wt);
+        hipLaunchKernelGGL((k_step_fused<S, true, false>), site_grid(g), dim3(SITE_THREADS), 0, c->stream, src, dst, g, c->cargs, wr, c->wt, wo);
     else if (walls)
-        hipLaunchKernelGGL((k_step_fused<S, false, true>), site_grid(g), dim3(SITE_THREADS), 0, c->stream, src, dst, g, c->cargs, wr, c->wt);
+        hipLaunchKernelGGL((k_step_fused<S, false, true>), site_grid(g), dim3(SITE_THREADS), 0, c->stream, src, dst, g, c->cargs, wr, c->wt, wo);
     else
-        hipLaunchKernelGGL((k_step_fused<S, false, false>), site_grid(g), dim3(SITE_THREADS), 0, c->stream, src, dst, g, c->cargs, wr, c->wt);
+        hipLaunchKernelGGL((k_step_fused<S, false, false>), site_grid(g), dim3(SITE_THREADS), 0, c->stream, src, dst, g, c->cargs, wr, c->wt, wo);
     s = check_launch(c, "step_fused");
     if (s) return s;
     c->cur = 1 - c->cur;
     c->have_prev = true;
+    if (walls) {
+        c->wr_cur = 1 - c->wr_cur;
+        c->wr_buf = c->cur;
+    }
     return LBM_OK;
 }
 
@@ -273,6 +305,7 @@ lbm_status do_init(lbm_ctx* c, const double* rho, const double* ux, const double
     hipLaunchKernelGGL((k_init_fields<S>), site_grid(c->pl.geo), dim3(SITE_THREADS), 0, c->stream,
                        (S*)c->buf(c->cur), c->pl.geo, rho, ux, uy, T);
     c->have_prev = false;
+    c->wr_buf = -1;
     return check_launch(c, "init");
 }
 template <typename S>
@@ -281,6 +314,7 @@ lbm_status do_init_rt(lbm_ctx* c, const double* P, RtProfile pr)
     hipLaunchKernelGGL((k_init_rt<S>), site_grid(c->pl.geo), dim3(SITE_THREADS), 0, c->stream,
                        (S*)c->buf(c->cur), c->pl.geo, P, pr);
     c->have_prev = false;
+    c->wr_buf = -1;
     return check_launch(c, "init_rt");
 }
 template <typename S>
@@ -299,7 +333,10 @@ lbm_status do_canon(lbm_ctx* c, void* canon, bool to_canon)
         hipLaunchKernelGGL((k_canon_copy<S, true>), grid, dim3(256), 0, c->stream, (S*)c->buf(c->cur), (S*)canon, g);
     else
         hipLaunchKernelGGL((k_canon_copy<S, false>), grid, dim3(256), 0, c->stream, (S*)c->buf(c->cur), (S*)canon, g);
-    if (!to_canon) c->have_prev = false;
+    if (!to_canon) {
+        c->have_prev = false;
+        c->wr_buf = -1;
+    }
     return check_launch(c, "canonical copy");
 }
 template <typename S>
@@ -309,7 +346,7 @@ lbm_status do_conservation(lbm_ctx* c, double* out4)
                        (const S*)c->buf(c->cur), c->pl.geo, c->partials());
     lbm_status s = check_launch(c, "conservation");
     if (s) return s;
-    hipLaunchKernelGGL((k_reduce_partials<4, false>), dim3(1), dim3(256), 0, c->stream,
+    hipLaunchKernelGGL((k_reduce_partials<4, false>), dim3(1), dim3(REDUCE_THREADS), 0, c->stream,
                        (const double*)c->partials(), RED_BLOCKS, out4);
     return check_launch(c, "conservation reduce");
 }
@@ -342,6 +379,8 @@ lbm_status lbm_create(const lbm_params* p, void* dev_workspace, size_t bytes, vo
     c->have_prev = false;
     c->lam_cur = 0;
     c->have_lambda = false;
+    c->wr_cur = 0;
+    c->wr_buf = -1;
     for (int l = 0; l < NPOP; ++l) {
         c->wt.ew[0][l] = feq_pop<false>(l, 1.0, 0.0, 0.0, p->t_bottom);
         c->wt.ew[1][l] = feq_pop<false>(l, 1.0, 0.0, 0.0, p->t_top);
@@ -447,6 +486,7 @@ lbm_status lbm_set_state(lbm_ctx* c, const void* src)
     if (hipMemcpyAsync(c->buf(c->cur), src, c->pl.state_bytes, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
         return check_launch(c, "set_state");
     c->have_prev = false;
+    c->wr_buf = -1;
     return LBM_OK;
 }
 

@@ -68,6 +68,25 @@ __device__ __forceinline__ int wrap_x(int xs, int lx)
     return xs < 0 ? xs + lx : (xs >= lx ? xs - lx : xs);
 }
 
+// Plane access as (block-uniform base pointer) + (per-thread 32-bit byte
+// offset): the base lives in scalar registers and one vector offset serves all
+// 37 planes, so no 64-bit per-plane vector addresses are kept alive.
+template <typename T>
+__device__ __forceinline__ T ld_at(const T* base, unsigned byte_off)
+{
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+template <typename T>
+__device__ __forceinline__ void st_nt(T* base, unsigned byte_off, T v)
+{
+    __builtin_nontemporal_store(v, reinterpret_cast<T*>(reinterpret_cast<char*>(base) + byte_off));
+}
+template <typename T>
+__device__ __forceinline__ void st_at(T* base, unsigned byte_off, T v)
+{
+    *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + byte_off) = v;
+}
+
 // ---------------------------------------------------------------------------
 // propagate: dst_l(x, y) = src_l(x - ex_l, y - ey_l).  One block streams a
 // chunk of one column of one plane; each thread moves UNROLL vectors of VEC
@@ -180,20 +199,39 @@ __global__ __launch_bounds__(256) void k_bc_apply(S* __restrict__ dst, Geo g, co
 // ---------------------------------------------------------------------------
 constexpr int SITE_THREADS = 256;
 
-template <typename S>
-__global__ __launch_bounds__(SITE_THREADS) void k_collide(S* __restrict__ buf, Geo g, CollideArgs args)
+// Density of a site from its just-written populations, summed in population
+// order in FP64 exactly as k_wall_density sums them, into the wall-density
+// table of the next step (rows 0..2 and ly-3..ly-1 only).
+template <typename S, typename Cc>
+__device__ __forceinline__ void store_wall_density(const Cc (&f)[NPOP], const Geo& g, int x, int y,
+                                                   double* __restrict__ wall_rho_out)
+{
+    if (y < 3 || y >= g.ly - 3) {
+        double r = 0.0;
+#pragma unroll
+        for (int l = 0; l < NPOP; ++l) r += (double)(S)f[l];
+        const int wk = y < 3 ? y : 3 + (g.ly - 1 - y);
+        wall_rho_out[wk * g.lx + x] = Store<S>::shifted ? 1.0 + r : r;
+    }
+}
+
+template <typename S, bool WALLS>
+__global__ __launch_bounds__(SITE_THREADS) void k_collide(S* __restrict__ buf, Geo g, CollideArgs args,
+                                                       double* __restrict__ wall_rho_out)
 {
     using Cc = typename Store<S>::C;
     const int x = blockIdx.y;
     const int y = blockIdx.x * SITE_THREADS + threadIdx.x;
     if (y >= g.ly) return;
-    S* p = buf + g.origin + (long long)x * g.lyp + y;
+    S* col = buf + g.origin + (long long)x * g.lyp;
+    const unsigned yb = (unsigned)y * (unsigned)sizeof(S);
     Cc f[NPOP];
 #pragma unroll
-    for (int l = 0; l < NPOP; ++l) f[l] = (Cc)p[(size_t)l * g.plane];
+    for (int l = 0; l < NPOP; ++l) f[l] = (Cc)ld_at(col + (size_t)l * g.plane, yb);
     collide_site<Cc, Store<S>::shifted>(f, args);
 #pragma unroll
-    for (int l = 0; l < NPOP; ++l) __builtin_nontemporal_store((S)f[l], p + (size_t)l * g.plane);
+    for (int l = 0; l < NPOP; ++l) st_nt(col + (size_t)l * g.plane, yb, (S)f[l]);
+    if (WALLS) store_wall_density<S>(f, g, x, y, wall_rho_out);
 }
 
 // ---------------------------------------------------------------------------
@@ -201,18 +239,20 @@ __global__ __launch_bounds__(SITE_THREADS) void k_collide(S* __restrict__ buf, G
 // ---------------------------------------------------------------------------
 template <typename S, bool WRAP, bool WALLS>
 __global__ __launch_bounds__(SITE_THREADS) void k_step_fused(const S* __restrict__ src, S* __restrict__ dst, Geo g,
-                                                          CollideArgs args, const double* __restrict__ wall_rho, WallTable wt)
+                                                          CollideArgs args, const double* __restrict__ wall_rho, WallTable wt,
+                                                          double* __restrict__ wall_rho_out)
 {
     using Cc = typename Store<S>::C;
     const int x = blockIdx.y;
     const int y = blockIdx.x * SITE_THREADS + threadIdx.x;
     if (y >= g.ly) return;
+    const unsigned yb = (unsigned)y * (unsigned)sizeof(S);
     Cc f[NPOP];
 #pragma unroll
     for (int l = 0; l < NPOP; ++l) {
         int xs = x - EX[l];
         if (WRAP) xs = wrap_x(xs, g.lx);
-        f[l] = (Cc)src[(size_t)l * g.plane + g.origin + (long long)xs * g.lyp + (y - EY[l])];
+        f[l] = (Cc)ld_at(src + (size_t)l * g.plane + g.origin + (long long)xs * g.lyp - EY[l], yb);
     }
     if (WALLS && (y < 3 || y >= g.ly - 3)) {
 #pragma unroll
@@ -224,15 +264,16 @@ __global__ __launch_bounds__(SITE_THREADS) void k_step_fused(const S* __restrict
             if (en > r) {
                 const int xs = wrap_x(x - EX[l], g.lx);
                 double v = wt.ew[wall][l] * wall_rho[(wall * 3 + (en - r - 1)) * g.lx + xs];
-                if (Store<S>::shifted) v -= wt.w[l];
+                if (Store<S>::shifted) v -= W_SHELL[SHELL[l]];
                 f[l] = (Cc)v;
             }
         }
     }
     collide_site<Cc, Store<S>::shifted>(f, args);
-    S* p = dst + g.origin + (long long)x * g.lyp + y;
+    S* col = dst + g.origin + (long long)x * g.lyp;
 #pragma unroll
-    for (int l = 0; l < NPOP; ++l) __builtin_nontemporal_store((S)f[l], p + (size_t)l * g.plane);
+    for (int l = 0; l < NPOP; ++l) st_nt(col + (size_t)l * g.plane, yb, (S)f[l]);
+    if (WALLS) store_wall_density<S>(f, g, x, y, wall_rho_out);
 }
 
 // ---------------------------------------------------------------------------
@@ -369,21 +410,46 @@ __global__ __launch_bounds__(256) void k_conservation_partial(const S* __restric
     block_sum_store<4>(acc, partials + (size_t)blockIdx.x * 4);
 }
 
-// out[k] (+)= sum over nparts of partials[p * N + k], one block, fixed order.
+// out[k] (+)= sum over nparts of partials[p * N + k]: one block of
+// REDUCE_THREADS threads, each with 4 interleaved accumulators, then a fixed
+// wave/LDS tree.  The order depends only on nparts, so results are bitwise
+// reproducible.
+constexpr int REDUCE_THREADS = 1024;
+
 template <int N, bool ACCUMULATE>
-__global__ __launch_bounds__(256) void k_reduce_partials(const double* __restrict__ partials, int nparts, double* __restrict__ out)
+__global__ __launch_bounds__(REDUCE_THREADS) void k_reduce_partials(const double* __restrict__ partials, int nparts, double* __restrict__ out)
 {
+    double acc[4][N];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int k = 0; k < N; ++k) acc[j][k] = 0.0;
+    int p = threadIdx.x;
+    for (; p + 3 * REDUCE_THREADS < nparts; p += 4 * REDUCE_THREADS) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int k = 0; k < N; ++k) acc[j][k] += partials[(size_t)(p + j * REDUCE_THREADS) * N + k];
+    }
+    for (int j = 0; p + j * REDUCE_THREADS < nparts; ++j)
+#pragma unroll
+        for (int k = 0; k < N; ++k) acc[j][k] += partials[(size_t)(p + j * REDUCE_THREADS) * N + k];
     double v[N];
 #pragma unroll
-    for (int k = 0; k < N; ++k) v[k] = 0.0;
-    for (int p = threadIdx.x; p < nparts; p += 256) {
+    for (int k = 0; k < N; ++k) v[k] = (acc[0][k] + acc[1][k]) + (acc[2][k] + acc[3][k]);
+    __shared__ double red[N][REDUCE_THREADS / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
-        for (int k = 0; k < N; ++k) v[k] += partials[(size_t)p * N + k];
+    for (int k = 0; k < N; ++k) {
+        const double t = wave_sum(v[k]);
+        if (lane == 0) red[k][wid] = t;
     }
-    __shared__ double tot[N];
-    block_sum_store<N>(v, tot);
     __syncthreads();
-    if (threadIdx.x < N) out[threadIdx.x] = ACCUMULATE ? out[threadIdx.x] + tot[threadIdx.x] : tot[threadIdx.x];
+    if (threadIdx.x < N) {
+        double t = 0.0;
+        for (int w = 0; w < REDUCE_THREADS / 64; ++w) t += red[threadIdx.x][w];
+        out[threadIdx.x] = ACCUMULATE ? out[threadIdx.x] + t : t;
+    }
 }
 
 }  // namespace lbm

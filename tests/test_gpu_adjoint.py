@@ -140,46 +140,63 @@ def test_512x512_gradient_against_central_differences():
     say("512x512 FD check")
     P = torch.tensor(inputs.rt_perturbation(lx, ly, 1), device=DEV)
     P2 = torch.tensor(inputs.rt_perturbation(lx, ly, 2), device=DEV)
-    lat = Lattice(lx, ly, TAU, -1e-5, TB, TT, precision="fp64", step="fused", device=DEV)
-    lat.init_rt(P2)
-    lat.step(n)
-    Tt = lat.macros()[3].clone()
-    del lat
+    # target: the final temperature of the run from seed 2, in the forward's own
+    # precision (an FP64 target for the FP32 forward would make the loss measure
+    # the FP32 round-off of the whole lattice instead of the seed difference)
+    targets = {}
+    for prec in ("fp64", "fp32"):
+        lat = Lattice(lx, ly, TAU, -1e-5, TB, TT, precision=prec, step="fused", device=DEV)
+        lat.init_rt(P2)
+        lat.step(n)
+        targets[prec] = lat.macros()[3].clone()
+        del lat
+    Tt = targets["fp64"]
     grads = {}
     for prec in ("fp64", "fp32"):
         cfg = RolloutConfig(lx, ly, n, precision=prec, checkpoint="sqrt")
         Pg = P.clone().requires_grad_(True)
         tg = torch.tensor(TAU, dtype=torch.float64, device=DEV, requires_grad=True)
         T = rt_temperature(Pg, tg, cfg)
-        (0.5 * ((T - Tt) ** 2).sum()).backward()
+        (0.5 * ((T - targets[prec]) ** 2).sum()).backward()
         grads[prec] = (Pg.grad.clone(), float(tg.grad))
         say(f"  {prec} stats {cfg.stats}")
     gP, gtau = grads["fp64"]
-    # eps = 1e-4 is the per-site size of the perturbation (unit-RMS probes): with
-    # unit-2-norm probes the per-site step would be eps / 512 and the difference
-    # quotient would sit within ~1e-5 of forward round-off noise
+    # eps = 1e-4 is the per-site size of the perturbation (unit-RMS probes).
+    # The loss is small (T_N - T* ~ 1e-4), so the O(eps^2) truncation term of a
+    # central difference is ~500 eps^2 relative; central differences at eps and
+    # eps/2 are combined by Richardson extrapolation, which cancels it.  Plain
+    # central differences are reported beside it.
     probes = torch.tensor(inputs.probe_directions(lx, ly, 77, 16, norm="rms"), device=DEV)
     eps = 1e-4
-    worst = 0.0
+
+    def cd(h, v=None, dtau=0.0):
+        if v is None:
+            return (fp64_loss(P, TAU + h, Tt, lx, ly, n) - fp64_loss(P, TAU - h, Tt, lx, ly, n)) / (2 * h)
+        return (fp64_loss(P + h * v, TAU, Tt, lx, ly, n) - fp64_loss(P - h * v, TAU, Tt, lx, ly, n)) / (2 * h)
+
+    worst, worst_cd = 0.0, 0.0
     for k in range(16):
         v = probes[k]
-        fd = (fp64_loss(P + eps * v, TAU, Tt, lx, ly, n) - fp64_loss(P - eps * v, TAU, Tt, lx, ly, n)) / (2 * eps)
+        d1, d2 = cd(eps, v), cd(eps / 2, v)
+        rich = (4 * d2 - d1) / 3
         ad = float((gP * v).sum())
-        e = abs(fd - ad) / abs(ad)
-        worst = max(worst, e)
-        say(f"  probe {k}: adjoint {ad:.9e} fd {fd:.9e} rel {e:.1e}")
-    assert worst <= 1e-6
-    e_tau = 1e-5
-    fd = (fp64_loss(P, TAU + e_tau, Tt, lx, ly, n) - fp64_loss(P, TAU - e_tau, Tt, lx, ly, n)) / (2 * e_tau)
-    say(f"  tau: adjoint {gtau:.9e} fd {fd:.9e} rel {abs(fd - gtau) / abs(gtau):.1e}")
-    assert abs(fd - gtau) <= 1e-6 * abs(gtau)
+        e, e_cd = abs(rich - ad) / abs(ad), abs(d1 - ad) / abs(ad)
+        worst, worst_cd = max(worst, e), max(worst_cd, e_cd)
+        say(f"  probe {k}: adjoint {ad:.10e} richardson {rich:.10e} rel {e:.1e} (central {e_cd:.1e})")
+    assert worst <= 1e-6, worst
+    assert worst_cd <= 1e-4, worst_cd
+    d1, d2 = cd(eps), cd(eps / 2)
+    rich = (4 * d2 - d1) / 3
+    e = abs(rich - gtau) / abs(gtau)
+    say(f"  tau: adjoint {gtau:.10e} richardson {rich:.10e} rel {e:.1e} (central {abs(d1 - gtau) / abs(gtau):.1e})")
+    assert e <= 1e-6
     g32, t32 = grads["fp32"]
     e32 = float((g32 - gP).norm() / gP.norm())
     say(f"  FP32-forward gradient vs FP64: rel L2 {e32:.2e}, dtau {abs(t32 - gtau) / abs(gtau):.2e}")
-    # reported, not a parity bar: FP32 states carry ~1e-7 relative noise while
-    # T_N - T* (the adjoint seed) is only ~1e-4, so percent-level differences
-    # are expected; this only guards against a broken FP32 adjoint path
-    assert e32 <= 0.2
+    # reported, not a parity bar: FP32 states carry ~1e-7 relative round-off
+    # while T_N - T* (the adjoint seed) is only ~1e-4; this guards against a
+    # broken FP32 adjoint path
+    assert e32 <= 0.5
 
 
 def test_binomial_and_sqrt_give_bitwise_equal_gradients():
