@@ -84,6 +84,13 @@ def run(args):
     del lat
     torch.cuda.empty_cache()
 
+    log("bench: FP64 fused step, planes layout")
+    lat = Lattice(lx, ly, tau, g, tb, tt, precision="fp64", step="fused", layout="planes", device=dev)
+    lat.init_rt(P)
+    planes_mlups, _ = mlups(lat, max(50, args.steps // 5), 10)
+    del lat
+    torch.cuda.empty_cache()
+
     log("bench: FP64 split step and its kernels")
     lat = make("fp64", "split")
     split_mlups, _ = mlups(lat, max(20, args.steps // 10), 5)
@@ -128,10 +135,11 @@ def run(args):
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"D2Q37 Rayleigh-Taylor {lx}x{ly} FP64, walls, tau=0.7, g=-1e-5",
-                   "lx": lx, "ly": ly, "step": "fused gather+bc+collide"},
+                   "lx": lx, "ly": ly, "step": "fused gather+bc+collide", "layout": "columns"},
         "fp32_shifted_mlups": round(fp32_mlups, 1),
         "fp32_over_fp64": round(fp32_mlups / fp64_mlups, 3),
         "fp64_split_mlups": round(split_mlups, 1),
+        "fp64_fused_planes_layout_mlups": round(planes_mlups, 1),
         "adjoint_over_forward_fp32": round(t_adj / t_fwd32, 3),
         "kernel_ms": {"fused_fp64": round(t_fused * 1e3, 4), "fused_fp32": round(t_fused32 * 1e3, 4),
                       "propagate_fp64": round(t_prop * 1e3, 4), "collide_fp64": round(t_coll * 1e3, 4),

@@ -73,6 +73,13 @@ typedef enum { LBM_X_WRAP = 0, LBM_X_HALO = 1 } lbm_xmode;
  * gather-collide pass (eq. (4) evaluated per site). Results are identical up
  * to rounding order (none: both evaluate the same expressions). */
 typedef enum { LBM_STEP_SPLIT = 0, LBM_STEP_FUSED = 1 } lbm_step_kind;
+/* Population storage.  Both keep every (population, column) segment
+ * contiguous in y with 128-byte aligned rows (the paper's column-major
+ * order, section 4): PLANES stores population l of all columns together
+ * (structure of arrays); COLUMNS stores the 37 segments of a column together,
+ * so the 37 streams a site touches lie within one column (better DRAM
+ * locality).  Results are identical. */
+typedef enum { LBM_LAYOUT_PLANES = 0, LBM_LAYOUT_COLUMNS = 1 } lbm_layout;
 
 typedef struct {
     int32_t lx, ly;        /* lattice sites; lx >= 7, ly >= 7               */
@@ -81,7 +88,7 @@ typedef struct {
     int32_t xmode;         /* lbm_xmode                                      */
     int32_t step_kind;     /* lbm_step_kind                                  */
     int32_t adjoint;       /* nonzero: also reserve the adjoint buffers      */
-    int32_t reserved;      /* must be 0                                      */
+    int32_t layout;        /* lbm_layout                                     */
     double tau;            /* relaxation time, > 0.5                         */
     double g_y;            /* gravity, lattice units per step (y component)  */
     double t_bottom;       /* wall temperatures (ignored for LBM_Y_PERIODIC) */

@@ -144,19 +144,19 @@ __global__ __launch_bounds__(SITE_THREADS) void k_adj_collide_push(
         // precision; all loads unconditional -- wall slots read ghost rows and
         // are replaced below)
         double lam[NPOP];
-        const double* lcol = lam_in + lg.origin + (long long)x * lg.lyp;
+        const double* lcol = lam_in + lg.origin + (long long)x * lg.cs;
 #pragma unroll
-        for (int l = 0; l < NPOP; ++l) lam[l] = ld_at(lcol + (size_t)l * lg.plane, yd);
+        for (int l = 0; l < NPOP; ++l) lam[l] = ld_at(lcol + (size_t)l * lg.ps, yd);
         Cc gl[NPOP];
 #pragma unroll
         for (int l = 0; l < NPOP; ++l) {
             int xs = wrap_x(x - EX[l], g.lx);
             if (WALLS) {
-                gl[l] = (Cc)ld_at(fn + (size_t)l * g.plane + g.origin + (long long)xs * g.lyp - EY[l], yb);
+                gl[l] = (Cc)ld_at(fn + (size_t)l * g.ps + g.origin + (long long)xs * g.cs - EY[l], yb);
             } else {
                 int ys = y - EY[l];
                 ys = ys < 0 ? ys + g.ly : (ys >= g.ly ? ys - g.ly : ys);
-                gl[l] = (Cc)fn[(size_t)l * g.plane + g.origin + (long long)xs * g.lyp + ys];
+                gl[l] = (Cc)fn[(size_t)l * g.ps + g.origin + (long long)xs * g.cs + ys];
             }
         }
         // raw moments of g and Lg = sum_l lambda_l g_l, in FP64
@@ -197,11 +197,11 @@ __global__ __launch_bounds__(SITE_THREADS) void k_adj_collide_push(
         for (int l = 0; l < NPOP; ++l) {
             const int xd = wrap_x(x - EX[l], g.lx);
             if (WALLS) {
-                st_at(lam_out + (size_t)l * lg.plane + lg.origin + (long long)xd * lg.lyp - EY[l], yd, lam[l]);
+                st_at(lam_out + (size_t)l * lg.ps + lg.origin + (long long)xd * lg.cs - EY[l], yd, lam[l]);
             } else {
                 int ys = y - EY[l];
                 ys = ys < 0 ? ys + g.ly : (ys >= g.ly ? ys - g.ly : ys);
-                lam_out[(size_t)l * lg.plane + lg.origin + (long long)xd * lg.lyp + ys] = lam[l];
+                lam_out[(size_t)l * lg.ps + lg.origin + (long long)xd * lg.cs + ys] = lam[l];
             }
         }
     }
@@ -219,19 +219,19 @@ __global__ __launch_bounds__(256) void k_adj_bc_fix(double* __restrict__ lam, Ge
     const int wall = wr / 3, r = wr % 3;
     const int y = wall == 0 ? r : lg.ly - 1 - r;
     const int yg = wall == 0 ? -r - 1 : lg.ly + r;
-    double* col = lam + lg.origin + (long long)x * lg.lyp;
+    double* col = lam + lg.origin + (long long)x * lg.cs;
     double gh[NPOP], in[NPOP];
 #pragma unroll
     for (int l = 0; l < NPOP; ++l) {
         const int en = wall == 0 ? EY[l] : -EY[l];
-        gh[l] = (en >= r + 1) ? col[(size_t)l * lg.plane + yg] : 0.0;
-        in[l] = (-en > r) ? 0.0 : col[(size_t)l * lg.plane + y];
+        gh[l] = (en >= r + 1) ? col[(size_t)l * lg.ps + yg] : 0.0;
+        in[l] = (-en > r) ? 0.0 : col[(size_t)l * lg.ps + y];
     }
     double beta = 0.0;
 #pragma unroll
     for (int l = 0; l < NPOP; ++l) beta += wt.ew[wall][l] * gh[l];
 #pragma unroll
-    for (int l = 0; l < NPOP; ++l) col[(size_t)l * lg.plane + y] = in[l] + beta;
+    for (int l = 0; l < NPOP; ++l) col[(size_t)l * lg.ps + y] = in[l] + beta;
 }
 
 // lambda_l = d(x,y) dT/df_l = d (|xi_l - u|^2 - 2T) / (2 rho), with
@@ -245,15 +245,15 @@ __global__ __launch_bounds__(SITE_THREADS) void k_adj_seed_T(const S* __restrict
     double loss = 0.0;
     if (y < g.ly) {
         double rho, ux, uy, T;
-        site_macros<S>(fbuf + g.origin + (long long)x * g.lyp + y, g.plane, rho, ux, uy, T);
+        site_macros<S>(fbuf + g.origin + (long long)x * g.cs + y, g.ps, rho, ux, uy, T);
         double d = d_in[(long long)x * g.ly + y];
         if (LOSS) { d = T - d; loss = 0.5 * d * d; }
         const double k = d / (2.0 * rho);
-        double* lp = lam + lg.origin + (long long)x * lg.lyp + y;
+        double* lp = lam + lg.origin + (long long)x * lg.cs + y;
 #pragma unroll
         for (int l = 0; l < NPOP; ++l) {
             const double dx = C * EX[l] - ux, dy = C * EY[l] - uy;
-            lp[(size_t)l * lg.plane] = k * (dx * dx + dy * dy - 2.0 * T);
+            lp[(size_t)l * lg.ps] = k * (dx * dx + dy * dy - 2.0 * T);
         }
     }
     if (LOSS) block_sum1(loss, partials);
@@ -276,14 +276,14 @@ __global__ __launch_bounds__(SITE_THREADS) void k_adj_init_rt(const double* __re
     const double dT = pr.t_amp * (1.0 - th_z * th_z) / pr.width;
     const double dr = -pr.p0 / (T0 * T0) * dT;
     const double th = T0 - 1.0;
-    const double* lp = lam + lg.origin + (long long)x * lg.lyp + y;
+    const double* lp = lam + lg.origin + (long long)x * lg.cs + y;
     double acc = 0.0;
 #pragma unroll
     for (int l = 0; l < NPOP; ++l) {
         const int sh = SHELL[l];
         const double Pl = 1.0 + th * (K::k1(sh) + th * K::k3(sh));
         const double dPl = K::k1(sh) + 2.0 * th * K::k3(sh);
-        acc += lp[(size_t)l * lg.plane] * W_SHELL[sh] * (Pl * dr + r0 * dPl * dT);
+        acc += lp[(size_t)l * lg.ps] * W_SHELL[sh] * (Pl * dr + r0 * dPl * dT);
     }
     dP[s] = acc;
 }

@@ -33,7 +33,7 @@ struct Plan {
     size_t total;
 };
 
-Geo make_geo(int lx, int ly, size_t elem)
+Geo make_geo(int lx, int ly, size_t elem, int layout)
 {
     Geo g;
     g.lx = lx;
@@ -41,8 +41,17 @@ Geo make_geo(int lx, int ly, size_t elem)
     g.g = (int)(128 / elem);                             // 128-byte aligned row 0
     const int col_align = (int)(128 / elem);
     g.lyp = (int)align_up((size_t)ly + 2 * g.g, (size_t)col_align);
-    g.origin = (long long)HALO_X * g.lyp + g.g;
-    g.plane = (long long)align_up((size_t)(lx + 2 * HALO_X) * g.lyp * elem, ALIGN) / (long long)elem;
+    const long long ncol = lx + 2 * HALO_X;
+    if (layout == LBM_LAYOUT_PLANES) {
+        g.cs = g.lyp;
+        g.ps = (long long)align_up((size_t)ncol * g.lyp * elem, ALIGN) / (long long)elem;
+        g.total = NPOP * g.ps;
+    } else {
+        g.ps = g.lyp;
+        g.cs = (long long)NPOP * g.lyp;
+        g.total = ncol * g.cs;
+    }
+    g.origin = (long long)HALO_X * g.cs + g.g;
     return g;
 }
 
@@ -55,7 +64,7 @@ bool valid(const lbm_params* p)
     if (p->ybc != LBM_Y_WALLS && p->ybc != LBM_Y_PERIODIC) return false;
     if (p->xmode != LBM_X_WRAP && p->xmode != LBM_X_HALO) return false;
     if (p->step_kind != LBM_STEP_SPLIT && p->step_kind != LBM_STEP_FUSED) return false;
-    if (p->reserved != 0) return false;
+    if (p->layout != LBM_LAYOUT_PLANES && p->layout != LBM_LAYOUT_COLUMNS) return false;
     if ((long long)p->lx * p->ly > (1LL << 31)) return false;
     return true;
 }
@@ -64,16 +73,16 @@ Plan plan(const lbm_params* p)
 {
     Plan pl{};
     pl.elem = p->precision == LBM_FP64 ? 8 : 4;
-    pl.geo = make_geo(p->lx, p->ly, pl.elem);
-    pl.lgeo = make_geo(p->lx, p->ly, 8);
-    pl.state_bytes = align_up((size_t)NPOP * pl.geo.plane * pl.elem, ALIGN);
+    pl.geo = make_geo(p->lx, p->ly, pl.elem, p->layout);
+    pl.lgeo = make_geo(p->lx, p->ly, 8, p->layout);
+    pl.state_bytes = align_up((size_t)pl.geo.total * pl.elem, ALIGN);
     size_t off = 0;
     pl.off_buf[0] = off; off += pl.state_bytes;
     pl.off_buf[1] = off; off += pl.state_bytes;
     pl.off_wall = off; off += 2 * align_up(6 * (size_t)p->lx * 8, ALIGN);
     pl.off_part = off; off += align_up(((size_t)RED_BLOCKS * 4 + 2) * 8, ALIGN);
     if (p->adjoint) {
-        const size_t lb = align_up((size_t)NPOP * pl.lgeo.plane * 8, ALIGN);
+        const size_t lb = align_up((size_t)pl.lgeo.total * 8, ALIGN);
         pl.off_lam[0] = off; off += lb;
         pl.off_lam[1] = off; off += lb;
         const size_t nb = (size_t)((p->ly + SITE_THREADS - 1) / SITE_THREADS) * p->lx;
@@ -137,6 +146,8 @@ void set_collide_args(lbm_ctx* c)
     c->cargs.omega = 1.0 / tau;
     c->cargs.tau_g = tau * g;
     c->cargs.grav_th = tau * (1.0 - tau) * g * g / 2.0;
+    c->cargs.g = g;
+    c->cargs.g_f = (float)g;
     c->cargs.omega_f = (float)c->cargs.omega;
     c->cargs.tau_g_f = (float)c->cargs.tau_g;
     c->cargs.grav_th_f = (float)c->cargs.grav_th;

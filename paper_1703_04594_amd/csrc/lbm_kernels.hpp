@@ -1,12 +1,14 @@
 // lbm_kernels.hpp -- gfx950 kernels of the D2Q37 step (forward).
 //
-// Storage: two population buffers in a padded structure-of-arrays layout.
-// Plane l holds population l of every site; inside a plane the lattice is
-// column-major with y fastest (the paper's column-major choice, section 4),
-// each column padded with G ghost rows on both sides (G * sizeof(S) = 128 B,
-// so interior row 0 of every column is 128-byte aligned) and the plane
-// carries 3 halo columns on both sides (hops reach 3 sites).  Site (x, y) of
-// plane l sits at  l * plane + origin + x * lyp + y.
+// Storage: two population buffers of padded columns.  A column segment holds
+// one population of one lattice column, y fastest (the paper's column-major
+// choice, section 4), padded with G ghost rows on both sides (G * sizeof(S) =
+// 128 B, so interior row 0 of every segment is 128-byte aligned); there are 3
+// halo columns on both sides (hops reach 3 sites).  Population l of site
+// (x, y) sits at  l * ps + origin + x * cs + y  with either
+//   planes:  ps = one whole plane, cs = lyp       (structure of arrays), or
+//   columns: ps = lyp,             cs = 37 * lyp  (the 37 segments of a column
+//            contiguous, so the 37 streams of a site lie within one column).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -18,10 +20,12 @@ namespace lbm {
 
 struct Geo {
     int lx, ly;       // interior sites
-    int lyp;          // padded column length (elements)
+    int lyp;          // padded column-segment length (elements)
     int g;            // ghost rows below / above (elements)
-    long long plane;  // elements per population plane
-    long long origin; // element index of site (0, 0) inside a plane
+    long long ps;     // stride between populations (elements)
+    long long cs;     // stride between columns (elements)
+    long long origin; // element index of population 0 at site (0, 0)
+    long long total;  // elements per buffer
 };
 
 constexpr int HALO_X = 3;
@@ -116,8 +120,8 @@ __global__ __launch_bounds__(PROP_THREADS) void k_propagate(const S* __restrict_
     const int ex = c_hops.ex[l], ey = c_hops.ey[l];
     int xs = x - ex;
     if (WRAP) xs = wrap_x(xs, g.lx);
-    const S* sp = src + (size_t)l * g.plane + g.origin + (long long)xs * g.lyp - ey;
-    S* dp = dst + (size_t)l * g.plane + g.origin + (long long)x * g.lyp;
+    const S* sp = src + (size_t)l * g.ps + g.origin + (long long)xs * g.cs - ey;
+    S* dp = dst + (size_t)l * g.ps + g.origin + (long long)x * g.cs;
     const int y0 = blockIdx.x * (PROP_THREADS * VEC * UNROLL) + threadIdx.x * VEC;
     VU v[UNROLL];
 #pragma unroll
@@ -143,10 +147,10 @@ __global__ __launch_bounds__(256) void k_fill_x_halo(S* __restrict__ buf, Geo g)
     if (ex == 0 || d >= (ex > 0 ? ex : -ex)) return;
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= g.lyp) return;
-    S* p = buf + (size_t)l * g.plane + g.origin - g.g + i;
+    S* p = buf + (size_t)l * g.ps + g.origin - g.g + i;
     const int to = ex > 0 ? -(d + 1) : g.lx + d;
     const int from = ex > 0 ? g.lx - (d + 1) : d;
-    p[(long long)to * g.lyp] = p[(long long)from * g.lyp];
+    p[(long long)to * g.cs] = p[(long long)from * g.cs];
 }
 
 // y ghost rows for LBM_Y_PERIODIC: rows [-3, 0) <- [ly-3, ly), [ly, ly+3) <- [0, 3).
@@ -157,7 +161,7 @@ __global__ __launch_bounds__(256) void k_fill_y_ghosts(S* __restrict__ buf, Geo 
     const int t = blockIdx.x * 256 + threadIdx.x;
     if (t >= g.lx * 6) return;
     const int x = t / 6, r = t % 6;
-    S* p = buf + (size_t)l * g.plane + g.origin + (long long)x * g.lyp;
+    S* p = buf + (size_t)l * g.ps + g.origin + (long long)x * g.cs;
     if (r < 3) p[r - 3] = p[g.ly - 3 + r];
     else p[g.ly + r - 3] = p[r - 3];
 }
@@ -172,10 +176,10 @@ __global__ __launch_bounds__(256) void k_wall_density(const S* __restrict__ buf,
     const int x = t % g.lx, wk = t / g.lx;
     const int wall = wk / 3, k = wk % 3;
     const int y = wall == 0 ? k : g.ly - 1 - k;
-    const S* p = buf + g.origin + (long long)x * g.lyp + y;
+    const S* p = buf + g.origin + (long long)x * g.cs + y;
     double r = 0.0;
 #pragma unroll
-    for (int l = 0; l < NPOP; ++l) r += (double)p[(size_t)l * g.plane];
+    for (int l = 0; l < NPOP; ++l) r += (double)p[(size_t)l * g.ps];
     wall_rho[t] = Store<S>::shifted ? 1.0 + r : r;
 }
 
@@ -191,7 +195,7 @@ __global__ __launch_bounds__(256) void k_bc_apply(S* __restrict__ dst, Geo g, co
     const int xs = wrap_x(x - c_hops.ex[l], g.lx);
     double v = wt.ew[wall][l] * wall_rho[(wall * 3 + c_slots.k[j]) * g.lx + xs];
     if (Store<S>::shifted) v -= wt.w[l];
-    dst[(size_t)l * g.plane + g.origin + (long long)x * g.lyp + y] = (S)v;
+    dst[(size_t)l * g.ps + g.origin + (long long)x * g.cs + y] = (S)v;
 }
 
 // ---------------------------------------------------------------------------
@@ -223,14 +227,14 @@ __global__ __launch_bounds__(SITE_THREADS) void k_collide(S* __restrict__ buf, G
     const int x = blockIdx.y;
     const int y = blockIdx.x * SITE_THREADS + threadIdx.x;
     if (y >= g.ly) return;
-    S* col = buf + g.origin + (long long)x * g.lyp;
+    S* col = buf + g.origin + (long long)x * g.cs;
     const unsigned yb = (unsigned)y * (unsigned)sizeof(S);
     Cc f[NPOP];
 #pragma unroll
-    for (int l = 0; l < NPOP; ++l) f[l] = (Cc)ld_at(col + (size_t)l * g.plane, yb);
+    for (int l = 0; l < NPOP; ++l) f[l] = (Cc)ld_at(col + (size_t)l * g.ps, yb);
     collide_site<Cc, Store<S>::shifted>(f, args);
 #pragma unroll
-    for (int l = 0; l < NPOP; ++l) st_nt(col + (size_t)l * g.plane, yb, (S)f[l]);
+    for (int l = 0; l < NPOP; ++l) st_nt(col + (size_t)l * g.ps, yb, (S)f[l]);
     if (WALLS) store_wall_density<S>(f, g, x, y, wall_rho_out);
 }
 
@@ -252,7 +256,7 @@ __global__ __launch_bounds__(SITE_THREADS) void k_step_fused(const S* __restrict
     for (int l = 0; l < NPOP; ++l) {
         int xs = x - EX[l];
         if (WRAP) xs = wrap_x(xs, g.lx);
-        f[l] = (Cc)ld_at(src + (size_t)l * g.plane + g.origin + (long long)xs * g.lyp - EY[l], yb);
+        f[l] = (Cc)ld_at(src + (size_t)l * g.ps + g.origin + (long long)xs * g.cs - EY[l], yb);
     }
     if (WALLS && (y < 3 || y >= g.ly - 3)) {
 #pragma unroll
@@ -270,9 +274,9 @@ __global__ __launch_bounds__(SITE_THREADS) void k_step_fused(const S* __restrict
         }
     }
     collide_site<Cc, Store<S>::shifted>(f, args);
-    S* col = dst + g.origin + (long long)x * g.lyp;
+    S* col = dst + g.origin + (long long)x * g.cs;
 #pragma unroll
-    for (int l = 0; l < NPOP; ++l) st_nt(col + (size_t)l * g.plane, yb, (S)f[l]);
+    for (int l = 0; l < NPOP; ++l) st_nt(col + (size_t)l * g.ps, yb, (S)f[l]);
     if (WALLS) store_wall_density<S>(f, g, x, y, wall_rho_out);
 }
 
@@ -289,9 +293,9 @@ __global__ __launch_bounds__(SITE_THREADS) void k_init_fields(S* __restrict__ bu
     if (y >= g.ly) return;
     const long long s = (long long)x * g.ly + y;
     const double r = rho[s], vx = ux[s], vy = uy[s], t = T[s];
-    S* p = buf + g.origin + (long long)x * g.lyp + y;
+    S* p = buf + g.origin + (long long)x * g.cs + y;
 #pragma unroll
-    for (int l = 0; l < NPOP; ++l) p[(size_t)l * g.plane] = (S)feq_pop<Store<S>::shifted>(l, r, vx, vy, t);
+    for (int l = 0; l < NPOP; ++l) p[(size_t)l * g.ps] = (S)feq_pop<Store<S>::shifted>(l, r, vx, vy, t);
 }
 
 struct RtProfile { double t_mid, t_amp, p0, width, y_mid; };
@@ -304,9 +308,9 @@ __global__ __launch_bounds__(SITE_THREADS) void k_init_rt(S* __restrict__ buf, G
     if (y >= g.ly) return;
     const double T0 = pr.t_mid - pr.t_amp * tanh((y - pr.y_mid - P[(long long)x * g.ly + y]) / pr.width);
     const double r0 = pr.p0 / T0;
-    S* p = buf + g.origin + (long long)x * g.lyp + y;
+    S* p = buf + g.origin + (long long)x * g.cs + y;
 #pragma unroll
-    for (int l = 0; l < NPOP; ++l) p[(size_t)l * g.plane] = (S)feq_pop<Store<S>::shifted>(l, r0, 0.0, 0.0, T0);
+    for (int l = 0; l < NPOP; ++l) p[(size_t)l * g.ps] = (S)feq_pop<Store<S>::shifted>(l, r0, 0.0, 0.0, T0);
 }
 
 // rho, u, T of eq. (2) in FP64.  Shifted storage uses the deviation form
@@ -340,7 +344,7 @@ __global__ __launch_bounds__(SITE_THREADS) void k_macros(const S* __restrict__ b
     const int y = blockIdx.x * SITE_THREADS + threadIdx.x;
     if (y >= g.ly) return;
     double r, vx, vy, t;
-    site_macros<S>(buf + g.origin + (long long)x * g.lyp + y, g.plane, r, vx, vy, t);
+    site_macros<S>(buf + g.origin + (long long)x * g.cs + y, g.ps, r, vx, vy, t);
     const long long s = (long long)x * g.ly + y;
     rho[s] = r; ux[s] = vx; uy[s] = vy; T[s] = t;
 }
@@ -352,7 +356,7 @@ __global__ __launch_bounds__(256) void k_canon_copy(S* __restrict__ buf, S* __re
     const int l = blockIdx.z, x = blockIdx.y;
     const int y = blockIdx.x * 256 + threadIdx.x;
     if (y >= g.ly) return;
-    const size_t pi = (size_t)l * g.plane + g.origin + (long long)x * g.lyp + y;
+    const size_t pi = (size_t)l * g.ps + g.origin + (long long)x * g.cs + y;
     const size_t ci = ((size_t)l * g.lx + x) * g.ly + y;
     if (TO_CANON) canon[ci] = buf[pi];
     else buf[pi] = canon[ci];
@@ -396,10 +400,10 @@ __global__ __launch_bounds__(256) void k_conservation_partial(const S* __restric
     const long long n = (long long)g.lx * g.ly;
     for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
         const int x = (int)(i / g.ly), y = (int)(i % g.ly);
-        const S* p = buf + g.origin + (long long)x * g.lyp + y;
+        const S* p = buf + g.origin + (long long)x * g.cs + y;
         double f[NPOP];
 #pragma unroll
-        for (int l = 0; l < NPOP; ++l) f[l] = (double)p[(size_t)l * g.plane];
+        for (int l = 0; l < NPOP; ++l) f[l] = (double)p[(size_t)l * g.ps];
         double m0, sx, sy, s2;
         hop_moments<double>(f, m0, sx, sy, s2);
         acc[0] += Store<S>::shifted ? 1.0 + m0 : m0;

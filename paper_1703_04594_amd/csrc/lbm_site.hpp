@@ -79,7 +79,8 @@ struct CollideArgs {
     double omega;    // 1 / tau
     double tau_g;    // tau * g_y   (velocity shift)
     double grav_th;  // tau (1 - tau) g_y^2 / 2   (temperature shift)
-    float omega_f, tau_g_f, grav_th_f;
+    double g;        // g_y
+    float omega_f, tau_g_f, grav_th_f, g_f;
 };
 
 template <typename C> __device__ __forceinline__ C arg_omega(const CollideArgs& a);
@@ -91,8 +92,23 @@ template <> __device__ __forceinline__ float arg_taug<float>(const CollideArgs& 
 template <typename C> __device__ __forceinline__ C arg_gth(const CollideArgs& a);
 template <> __device__ __forceinline__ double arg_gth<double>(const CollideArgs& a) { return a.grav_th; }
 template <> __device__ __forceinline__ float arg_gth<float>(const CollideArgs& a) { return a.grav_th_f; }
+template <typename C> __device__ __forceinline__ C arg_g(const CollideArgs& a);
+template <> __device__ __forceinline__ double arg_g<double>(const CollideArgs& a) { return a.g; }
+template <> __device__ __forceinline__ float arg_g<float>(const CollideArgs& a) { return a.g_f; }
 
 // BGK collision of one site, in place.  SHIFTED: f holds deviations d_l.
+//
+// In the shifted (FP32) form the relaxed populations are finally projected
+// back onto the exact post-collision moments.  In exact arithmetic the
+// equilibrium has the moments of f (mass, momentum plus tau*rho*g, energy
+// plus the work of the gravity shift), so the projection is zero; in FP32 the
+// rounded weights and scale break those identities by ~1e-8 per step, which
+// would otherwise drift mass and energy systematically.  The correction is
+// w_l (a + b ex + c ey + d |e|^2); its Gram matrix sum_l w_l v v^T with
+// v = (1, ex, ey, |e|^2) is fixed by the quadrature (sum w = 1,
+// sum w ex^2 = 1/c^2, sum w |e|^2 = 2/c^2, sum w |e|^4 = 8/c^4), which gives
+// a = 2 d0 - (c^2/2) d2, b = c^2 dx, c' = c^2 dy, d = -(c^2/2) d0 + (c^4/4) d2
+// for the moment defects (d0, dx, dy, d2).
 template <typename C, bool SHIFTED>
 __device__ __forceinline__ void collide_site(C (&f)[NPOP], const CollideArgs& args)
 {
@@ -103,15 +119,15 @@ __device__ __forceinline__ void collide_site(C (&f)[NPOP], const CollideArgs& ar
     const C rho = SHIFTED ? C(1) + m0 : m0;
     const C inv = C(1) / rho;
     const C ux = cscale<C>() * sx * inv;
-    C uy = cscale<C>() * sy * inv;
+    const C uy0 = cscale<C>() * sy * inv;   // velocity of f, before the gravity shift
     C th;
     if constexpr (SHIFTED) {
         // T - 1 = (sum (x2 - 2) d) / (2 rho) - u2 / 2
-        th = (c2scale<C>() * s2 - C(2) * m0) * inv * C(0.5) - (ux * ux + uy * uy) * C(0.5);
+        th = (c2scale<C>() * s2 - C(2) * m0) * inv * C(0.5) - (ux * ux + uy0 * uy0) * C(0.5);
     } else {
-        th = (c2scale<C>() * s2 * inv - (ux * ux + uy * uy)) * C(0.5) - C(1);
+        th = (c2scale<C>() * s2 * inv - (ux * ux + uy0 * uy0)) * C(0.5) - C(1);
     }
-    uy += arg_taug<C>(args);
+    const C uy = uy0 + arg_taug<C>(args);
     th += arg_gth<C>(args);
     const C u2 = ux * ux + uy * uy;
     const C cux = cscale<C>() * ux, cuy = cscale<C>() * uy;
@@ -147,6 +163,27 @@ __device__ __forceinline__ void collide_site(C (&f)[NPOP], const CollideArgs& ar
             feq = wshell<C>(s) * rho * (C(1) + pm);
         }
         f[l] = f[l] + omega * (feq - f[l]);
+    }
+    if constexpr (SHIFTED) {
+        const C g = arg_g<C>(args);
+        C M0, MX, MY, M2;
+        hop_moments<C>(f, M0, MX, MY, M2);
+        const C c2 = c2scale<C>();
+        const C d0 = m0 - M0;
+        const C dx = sx - MX;
+        const C dy = sy + rho * g / cscale<C>() - MY;
+        const C d2 = s2 + rho * (C(2) * g * uy0 + g * g) / c2 - M2;
+        const C ka = C(2) * d0 - C(0.5) * c2 * d2;
+        const C kb = c2 * dx, kc = c2 * dy;
+        const C kd = C(-0.5) * c2 * d0 + C(0.25) * c2 * c2 * d2;
+#pragma unroll
+        for (int l = 0; l < NPOP; ++l) {
+            C corr = ka;
+            if (EX[l] != 0) corr += C(EX[l]) * kb;
+            if (EY[l] != 0) corr += C(EY[l]) * kc;
+            if (R2_OF(l) != 0) corr += C(R2_OF(l)) * kd;
+            f[l] += wshell<C>(SHELL[l]) * corr;
+        }
     }
 }
 

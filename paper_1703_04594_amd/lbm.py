@@ -22,11 +22,13 @@ FP64, FP32_SHIFTED = 0, 1
 Y_WALLS, Y_PERIODIC = 0, 1
 X_WRAP, X_HALO = 0, 1
 STEP_SPLIT, STEP_FUSED = 0, 1
+LAYOUT_PLANES, LAYOUT_COLUMNS = 0, 1
 
 _PREC = {"fp64": FP64, "fp32": FP32_SHIFTED, "fp32_shifted": FP32_SHIFTED}
 _YBC = {"walls": Y_WALLS, "periodic": Y_PERIODIC}
 _XMODE = {"wrap": X_WRAP, "halo": X_HALO}
 _STEP = {"split": STEP_SPLIT, "fused": STEP_FUSED}
+_LAYOUT = {"planes": LAYOUT_PLANES, "columns": LAYOUT_COLUMNS}
 
 
 class LBMError(RuntimeError):
@@ -36,7 +38,7 @@ class LBMError(RuntimeError):
 class Params(ctypes.Structure):
     _fields_ = [("lx", ctypes.c_int32), ("ly", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("ybc", ctypes.c_int32), ("xmode", ctypes.c_int32), ("step_kind", ctypes.c_int32),
-                ("adjoint", ctypes.c_int32), ("reserved", ctypes.c_int32), ("tau", ctypes.c_double),
+                ("adjoint", ctypes.c_int32), ("layout", ctypes.c_int32), ("tau", ctypes.c_double),
                 ("g_y", ctypes.c_double), ("t_bottom", ctypes.c_double), ("t_top", ctypes.c_double)]
 
 
@@ -129,9 +131,9 @@ def scale_c() -> float:
 
 
 def make_params(lx, ly, tau, g_y=0.0, t_bottom=1.0, t_top=1.0, precision="fp64", ybc="walls",
-                xmode="wrap", step="split", adjoint=False) -> Params:
-    return Params(lx, ly, _PREC[precision], _YBC[ybc], _XMODE[xmode], _STEP[step], int(bool(adjoint)), 0,
-                  tau, g_y, t_bottom, t_top)
+                xmode="wrap", step="split", adjoint=False, layout="columns") -> Params:
+    return Params(lx, ly, _PREC[precision], _YBC[ybc], _XMODE[xmode], _STEP[step], int(bool(adjoint)),
+                  _LAYOUT[layout], tau, g_y, t_bottom, t_top)
 
 
 def workspace_bytes(p: Params) -> int:
@@ -151,12 +153,12 @@ class Lattice:
     """One D2Q37 lattice on one GPU (a context of liblbm.so)."""
 
     def __init__(self, lx, ly, tau, g_y=0.0, t_bottom=1.0, t_top=1.0, precision="fp64",
-                 ybc="walls", xmode="wrap", step="split", adjoint=False, device="cuda"):
+                 ybc="walls", xmode="wrap", step="split", adjoint=False, layout="columns", device="cuda"):
         self.L = lib()
         self.device = torch.device(device)
         if self.device.index is None:
             self.device = torch.device("cuda", torch.cuda.current_device())
-        self.p = make_params(lx, ly, tau, g_y, t_bottom, t_top, precision, ybc, xmode, step, adjoint)
+        self.p = make_params(lx, ly, tau, g_y, t_bottom, t_top, precision, ybc, xmode, step, adjoint, layout)
         self.lx, self.ly = lx, ly
         self.precision = precision
         self.store_dtype = torch.float64 if _PREC[precision] == FP64 else torch.float32

@@ -36,12 +36,14 @@ def rel(a, b):
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("ybc", ["walls", "periodic"])
-def test_one_reverse_step_matches_autograd(precision, ybc):
+@pytest.mark.parametrize("layout", ["columns", "planes"])
+def test_one_reverse_step_matches_autograd(precision, ybc, layout):
     lx, ly, g = 24, 20, -1e-3
-    say(f"adjoint step {precision} {ybc}")
+    say(f"adjoint step {precision} {ybc} {layout}")
     noise = torch.tensor(inputs.population_noise(lx, ly, 31))
     lam1 = torch.tensor(inputs.population_noise(lx, ly, 32))
-    lat = Lattice(lx, ly, TAU, g, TB, TT, precision=precision, ybc=ybc, adjoint=True, device=DEV)
+    lat = Lattice(lx, ly, TAU, g, TB, TT, precision=precision, ybc=ybc, adjoint=True, layout=layout,
+                  device=DEV)
     if precision == "fp64":
         f_store = WT[:, None, None] * (1 + 0.05 * noise)
         f64 = f_store.clone()

@@ -38,10 +38,11 @@ MODES = [("split", "wrap"), ("split", "halo"), ("fused", "wrap"), ("fused", "hal
 @pytest.mark.parametrize("lx,ly", [(7, 7), (37, 45), (64, 129), (300, 1030)])
 @pytest.mark.parametrize("xmode", ["wrap", "halo"])
 @pytest.mark.parametrize("ybc", ["periodic", "walls"])
-def test_propagate_is_the_bitwise_permutation(lx, ly, xmode, ybc):
-    say(f"propagate permutation {lx}x{ly} {xmode} {ybc}")
+@pytest.mark.parametrize("layout", ["columns", "planes"])
+def test_propagate_is_the_bitwise_permutation(lx, ly, xmode, ybc, layout):
+    say(f"propagate permutation {lx}x{ly} {xmode} {ybc} {layout}")
     t = tagged(lx, ly)
-    lat = Lattice(lx, ly, TAU, ybc=ybc, xmode=xmode, device=DEV)
+    lat = Lattice(lx, ly, TAU, ybc=ybc, xmode=xmode, layout=layout, device=DEV)
     lat.set_pops(tg(t))
     lat.propagate()
     got = lat.get_pops().cpu().numpy()
@@ -106,12 +107,13 @@ def test_bc_matches_oracle():
 
 
 @pytest.mark.parametrize("step,xmode", MODES)
-def test_rt_run_256x128_matches_oracle(step, xmode):
+@pytest.mark.parametrize("layout", ["columns", "planes"])
+def test_rt_run_256x128_matches_oracle(step, xmode, layout):
     """The small Rayleigh-Taylor case: 256x128, walls, 50 steps, every 10."""
     lx, ly = 256, 128
-    say(f"RT 256x128 {step} {xmode}")
+    say(f"RT 256x128 {step} {xmode} {layout}")
     P = inputs.rt_perturbation(lx, ly, 1)
-    lat = Lattice(lx, ly, TAU, G, TB, TT, step=step, xmode=xmode, device=DEV)
+    lat = Lattice(lx, ly, TAU, G, TB, TT, step=step, xmode=xmode, layout=layout, device=DEV)
     lat.init_rt(tg(P))
     ref, _ = oracle_rt(lx, ly, 1, 0)
     err = relw(lat.get_pops().cpu().numpy(), ref.get_pops())
@@ -204,14 +206,15 @@ def test_uniform_rest_state_at_wall_temperature_stays():
 
 
 @pytest.mark.parametrize("step", ["split", "fused"])
-def test_fp32_shifted_against_fp64_oracle(step):
+@pytest.mark.parametrize("layout", ["columns", "planes"])
+def test_fp32_shifted_against_fp64_oracle(step, layout):
     """FP32 deviations: per-field error after 50 steps of the 256x128 RT run.
     FP32 rounding of deviations O(0.3 w) is ~2e-8 of rho per step; the bound
     below leaves an order of magnitude over 50 steps."""
     lx, ly = 256, 128
     say(f"fp32 RT {step}")
     P = inputs.rt_perturbation(lx, ly, 1)
-    lat = Lattice(lx, ly, TAU, G, TB, TT, precision="fp32", step=step, device=DEV)
+    lat = Lattice(lx, ly, TAU, G, TB, TT, precision="fp32", step=step, layout=layout, device=DEV)
     lat.init_rt(tg(P))
     lat.step(50)
     ref, _ = oracle_rt(lx, ly, 1, 50)
