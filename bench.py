@@ -29,6 +29,38 @@ FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 vector
 FP32_PEAK_TFLOPS = 157.3
 
 
+def kernel_source_sha256():
+    """Hash of the GPU kernel sources (to tell whether stored counters still apply)."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1703_04594_amd", "csrc")
+    files = sorted(glob.glob(os.path.join(csrc, "*.hpp")) + glob.glob(os.path.join(csrc, "*.hip"))
+                   + glob.glob(os.path.join(csrc, "*.inc")) + glob.glob(os.path.join(csrc, "*.h")))
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel_prefix):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    runs, or None if the kernels changed since they were taken."""
+    path = os.path.join(ROOT, "profiles", "d2q37_2048x4096_hbm_traffic.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+    except OSError:
+        return None
+    if rec.get("source_sha256") != kernel_source_sha256():
+        return None
+    for name, v in rec["kernels"].items():
+        if name.startswith(kernel_prefix):
+            return v["traffic_bytes"]
+    return None
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -106,17 +138,19 @@ def run(args):
     del lat
     torch.cuda.empty_cache()
 
-    log("bench: adjoint step (FP32 state, FP64 lambda)")
-    lat = make("fp32", "fused", adjoint=True)
-    lat.step(10)
-    st = lat.get_state()
-    lat.step(1)
-    dacc = torch.zeros((), dtype=torch.float64, device=dev)
-    lat.seed_temperature(torch.ones((lx, ly), dtype=torch.float64, device=dev))
-    t_adj = time_launches(lambda: lat.adjoint_step(st, dacc), s, 10)
-    t_fwd32 = time_launches(lambda: lat.step(1), s, 10)
-    del lat, st
-    torch.cuda.empty_cache()
+    t_adj = {}
+    for lam in ("fp64", "fp32"):
+        log(f"bench: adjoint step (FP32 state, {lam} lambda)")
+        lat = make("fp32", "fused", adjoint=lam)
+        lat.step(10)
+        st = lat.get_state()
+        lat.step(1)
+        dacc = torch.zeros((), dtype=torch.float64, device=dev)
+        lat.seed_temperature(torch.ones((lx, ly), dtype=torch.float64, device=dev))
+        t_adj[lam] = time_launches(lambda: lat.adjoint_step(st, dacc), s, 10)
+        t_fwd32 = time_launches(lambda: lat.step(1), s, 10)
+        del lat, st
+        torch.cuda.empty_cache()
 
     bytes_fp64 = 2 * 37 * 8 * sites   # one read + one write of every population
     bytes_fp32 = 2 * 37 * 4 * sites
@@ -140,17 +174,21 @@ def run(args):
         "fp32_over_fp64": round(fp32_mlups / fp64_mlups, 3),
         "fp64_split_mlups": round(split_mlups, 1),
         "fp64_fused_planes_layout_mlups": round(planes_mlups, 1),
-        "adjoint_over_forward_fp32": round(t_adj / t_fwd32, 3),
+        "adjoint_over_forward_fp32": round(t_adj["fp64"] / t_fwd32, 3),
+        "adjoint_over_forward_fp32_lambda32": round(t_adj["fp32"] / t_fwd32, 3),
         "kernel_ms": {"fused_fp64": round(t_fused * 1e3, 4), "fused_fp32": round(t_fused32 * 1e3, 4),
                       "propagate_fp64": round(t_prop * 1e3, 4), "collide_fp64": round(t_coll * 1e3, 4),
-                      "adjoint_step_fp32": round(t_adj * 1e3, 4), "step_fp32": round(t_fwd32 * 1e3, 4)},
+                      "adjoint_step_fp32": round(t_adj["fp64"] * 1e3, 4),
+                      "adjoint_step_fp32_lambda32": round(t_adj["fp32"] * 1e3, 4), "step_fp32": round(t_fwd32 * 1e3, 4)},
         "hbm_frac": {"fused_fp64": round(bytes_fp64 / t_fused / 1e9 / HBM_PEAK_GBS, 3),
                      "fused_fp32": round(bytes_fp32 / t_fused32 / 1e9 / HBM_PEAK_GBS, 3),
                      "propagate_fp64": round(bytes_fp64 / t_prop / 1e9 / HBM_PEAK_GBS, 3),
                      "collide_fp64": round(bytes_fp64 / t_coll / 1e9 / HBM_PEAK_GBS, 3)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "k_step_fused<double,wrap,walls>", "bytes_per_site": 592},
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic("lbm::k_step_fused<double, true, true>") if (lx, ly) == (2048, 4096) else None,
+                     "kernel": "k_step_fused<double,wrap,walls>", "bytes_per_site": 592,
+                     "algorithmic_bytes_per_launch": bytes_fp64},
     }
     return res
 
@@ -196,7 +234,7 @@ def fp32_accuracy(args, nsteps=5000, every=500):
     return rows
 
 
-def adjoint_at_scale(lx=1024, ly=2048, nsteps=10000, budget=32 << 30):
+def adjoint_at_scale(lx=1024, ly=2048, nsteps=10000, budget=32 << 30, lam="fp64"):
     """Gradient of 1/2 sum (T_N - T*)^2 w.r.t. the initial perturbation field
     P and tau on the 1024x2048 lattice, FP32 forward states, FP64 adjoint,
     binomial checkpointing with all stored states inside `budget` bytes."""
@@ -221,7 +259,7 @@ def adjoint_at_scale(lx=1024, ly=2048, nsteps=10000, budget=32 << 30):
     torch.cuda.synchronize()
     t_fwd = time.perf_counter() - t0
     del lat
-    probe = Lattice(lx, ly, 0.7, -1e-5, 4 / 3, 2 / 3, precision="fp32", step="fused", adjoint=True, device=dev)
+    probe = Lattice(lx, ly, 0.7, -1e-5, 4 / 3, 2 / 3, precision="fp32", step="fused", adjoint=lam, device=dev)
     probe.init_rt(P)
     ws_bytes = probe.workspace.numel()
     st = probe.get_state()
@@ -235,7 +273,7 @@ def adjoint_at_scale(lx=1024, ly=2048, nsteps=10000, budget=32 << 30):
     torch.cuda.empty_cache()
     # full gradient: forward with checkpoints + reverse sweep
     cfg = RolloutConfig(lx, ly, nsteps, precision="fp32", checkpoint="binomial",
-                        memory_budget=budget - ws_bytes)
+                        memory_budget=budget - ws_bytes, lambda_precision=lam)
     torch.cuda.reset_peak_memory_stats()
     base_mem = torch.cuda.memory_allocated()
     Pg = P.clone().requires_grad_(True)
@@ -248,14 +286,14 @@ def adjoint_at_scale(lx=1024, ly=2048, nsteps=10000, budget=32 << 30):
     torch.cuda.synchronize()
     t_grad = time.perf_counter() - t0
     peak = torch.cuda.max_memory_allocated() - base_mem
-    out = {"lattice": f"{lx}x{ly}", "steps": nsteps, "checkpoint": "binomial",
+    out = {"lattice": f"{lx}x{ly}", "steps": nsteps, "checkpoint": "binomial", "lambda": lam,
            "budget_GB": round(budget / 2 ** 30, 1), "state_MB": round(state_bytes / 2 ** 20, 1),
            "snapshot_slots": cfg.stats.get("slots"), "forward_steps_total": cfg.stats.get("forward_steps"),
            "adjoint_step_ms": round(t_adj * 1e3, 4), "forward_step_ms": round(t_step * 1e3, 4),
            "adjoint_over_forward_step": round(t_adj / t_step, 3),
            "forward_wall_s": round(t_fwd, 3), "gradient_wall_s": round(t_grad, 3),
            "gradient_over_forward_wall": round(t_grad / t_fwd, 3),
-           "peak_memory_GB": round(peak / 2 ** 30, 2), "loss": float(loss),
+           "peak_memory_GB": round(peak / 2 ** 30, 2), "loss": float(loss.detach()),
            "dL_dtau": float(tg.grad), "dL_dP_norm": float(Pg.grad.norm())}
     log(f"bench: adjoint at scale {out}")
     return out
@@ -352,6 +390,7 @@ def main():
     if not args.skip_reports:
         res["fp32_accuracy_5000_steps"] = fp32_accuracy(args)
         res["adjoint_1024x2048_10000_steps"] = adjoint_at_scale()
+        res["adjoint_1024x2048_10000_steps_lambda32"] = adjoint_at_scale(lam="fp32")
     res["cpu_baseline"] = None if args.skip_cpu else cpu_baseline(args)
     print(json.dumps(res), flush=True)
 

@@ -87,7 +87,9 @@ typedef struct {
     int32_t ybc;           /* lbm_ybc                                        */
     int32_t xmode;         /* lbm_xmode                                      */
     int32_t step_kind;     /* lbm_step_kind                                  */
-    int32_t adjoint;       /* nonzero: also reserve the adjoint buffers      */
+    int32_t adjoint;       /* 0: none; 1: adjoint buffers with FP64 lambda;  */
+                           /* 2: FP32 lambda storage (arithmetic, d/dtau and */
+                           /*    dL/dP stay FP64)                            */
     int32_t layout;        /* lbm_layout                                     */
     double tau;            /* relaxation time, > 0.5                         */
     double g_y;            /* gravity, lattice units per step (y component)  */
@@ -155,7 +157,8 @@ lbm_status lbm_get_macros(lbm_ctx* ctx, double* rho, double* ux, double* uy, dou
  * the "previous buffer" so lbm_bc needs a propagate first. */
 lbm_status lbm_get_pops(lbm_ctx* ctx, void* dst);
 lbm_status lbm_set_pops(lbm_ctx* ctx, const void* src);
-/* Opaque padded-state snapshots, lbm_state_bytes each (device). */
+/* Opaque snapshots, lbm_state_bytes each (device): the padded population
+ * buffer followed by the densities of its 3 rows next to each wall. */
 lbm_status lbm_get_state(lbm_ctx* ctx, void* dst);
 lbm_status lbm_set_state(lbm_ctx* ctx, const void* src);
 /* Lattice totals of the collision invariants, accumulated in FP64 with a
@@ -164,8 +167,8 @@ lbm_status lbm_set_state(lbm_ctx* ctx, const void* src);
 lbm_status lbm_conservation(lbm_ctx* ctx, double* dev_out4);
 
 /* ---- adjoint (requires params.adjoint != 0) ------------------------------- */
-/* The adjoint state lambda = dL/df (FP64, one value per population and site)
- * lives in the workspace.  A reverse sweep is: seed lambda_N, then for
+/* The adjoint state lambda = dL/df (one value per population and site; stored
+ * in FP64, or FP32 when params.adjoint == 2) lives in the workspace.  A reverse sweep is: seed lambda_N, then for
  * n = N-1 .. 0 call lbm_adjoint_step with the forward state f_n, then
  * lbm_adjoint_init_rt for dL/dP. */
 

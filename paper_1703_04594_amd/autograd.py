@@ -34,6 +34,7 @@ class RolloutConfig:
     checkpoint: str = "sqrt"            # "sqrt" or "binomial"
     slots: int | None = None             # binomial: stored states
     memory_budget: int | None = None     # binomial: bytes for stored states (alternative to slots)
+    lambda_precision: str = "fp64"      # adjoint state storage: "fp64" or "fp32"
     profile: RtProfile = field(default_factory=RtProfile)
     stats: dict = field(default_factory=dict)
 
@@ -54,7 +55,7 @@ class RTRollout(torch.autograd.Function):
     @staticmethod
     def forward(ctx, P: torch.Tensor, tau: torch.Tensor, cfg: RolloutConfig):
         lat = Lattice(cfg.lx, cfg.ly, float(tau), cfg.g_y, cfg.t_bottom, cfg.t_top,
-                      precision=cfg.precision, step=cfg.step, adjoint=True, device=P.device)
+                      precision=cfg.precision, step=cfg.step, adjoint=cfg.lambda_precision, device=P.device)
         P = P.detach().contiguous()
         lat.init_rt(P, cfg.profile)
         sch = cfg.schedule(lat.state_bytes)

@@ -128,25 +128,25 @@ __device__ __forceinline__ void block_sum1(double v, double* __restrict__ partia
     block_sum_store<1>(a, partials + (size_t)blockIdx.y * gridDim.x + blockIdx.x);
 }
 
-template <typename S, bool WALLS>
+template <typename S, typename L, bool WALLS>
 __global__ __launch_bounds__(SITE_THREADS) void k_adj_collide_push(
-    const S* __restrict__ fn, Geo g, const double* __restrict__ lam_in, double* __restrict__ lam_out, Geo lg,
+    const S* __restrict__ fn, Geo g, const L* __restrict__ lam_in, L* __restrict__ lam_out, Geo lg,
     AdjArgs a, const double* __restrict__ wall_rho, WallTable wt, double* __restrict__ partials)
 {
-    const int x = blockIdx.y;
-    const int y = blockIdx.x * SITE_THREADS + threadIdx.x;
+    const SiteBlock sb = site_block(g);
+    const int x = sb.x, y = sb.y;
     double dtau = 0.0;
     if (y < g.ly) {
         using Cc = typename Store<S>::C;
         const unsigned yb = (unsigned)y * (unsigned)sizeof(S);
-        const unsigned yd = (unsigned)y * 8u;
+        const unsigned yd = (unsigned)y * (unsigned)sizeof(L);
         // lambda_{n+1} at this site and the raw gather of f_n (storage
         // precision; all loads unconditional -- wall slots read ghost rows and
         // are replaced below)
         double lam[NPOP];
-        const double* lcol = lam_in + lg.origin + (long long)x * lg.cs;
+        const L* lcol = lam_in + lg.origin + (long long)x * lg.cs;
 #pragma unroll
-        for (int l = 0; l < NPOP; ++l) lam[l] = ld_at(lcol + (size_t)l * lg.ps, yd);
+        for (int l = 0; l < NPOP; ++l) lam[l] = (double)ld_at(lcol + (size_t)l * lg.ps, yd);
         Cc gl[NPOP];
 #pragma unroll
         for (int l = 0; l < NPOP; ++l) {
@@ -197,51 +197,69 @@ __global__ __launch_bounds__(SITE_THREADS) void k_adj_collide_push(
         for (int l = 0; l < NPOP; ++l) {
             const int xd = wrap_x(x - EX[l], g.lx);
             if (WALLS) {
-                st_at(lam_out + (size_t)l * lg.ps + lg.origin + (long long)xd * lg.cs - EY[l], yd, lam[l]);
+                st_at(lam_out + (size_t)l * lg.ps + lg.origin + (long long)xd * lg.cs - EY[l], yd, (L)lam[l]);
             } else {
                 int ys = y - EY[l];
                 ys = ys < 0 ? ys + g.ly : (ys >= g.ly ? ys - g.ly : ys);
-                lam_out[(size_t)l * lg.ps + lg.origin + (long long)xd * lg.cs + ys] = lam[l];
+                lam_out[(size_t)l * lg.ps + lg.origin + (long long)xd * lg.cs + ys] = (L)lam[l];
             }
         }
     }
     block_sum1(dtau, partials);
 }
 
-// bc^T and the zeroing of slots nobody pushes to: thread per (wall, row, x).
-// All loads are issued before any store (the ghost rows read for beta and
-// the interior row written never overlap).
-__global__ __launch_bounds__(256) void k_adj_bc_fix(double* __restrict__ lam, Geo lg, WallTable wt)
+// bc^T and the zeroing of slots nobody pushes to.  A block handles one wall
+// and BCF_COLS columns, one thread per (column, population): each thread loads
+// its 3 ghost values (wall-slot mu pushed beyond the wall) and 3 interior
+// values, the ghost contributions E^w_l mu are summed over the 37 populations
+// of a column in LDS in fixed order (beta of each of the 3 rows), and every
+// interior value becomes (pushed ? value : 0) + beta.
+constexpr int BCF_COLS = 6;
+
+template <typename L>
+__global__ __launch_bounds__(256) void k_adj_bc_fix(L* __restrict__ lam, Geo lg, const WallTable* __restrict__ wt)
 {
-    const int t = blockIdx.x * 256 + threadIdx.x;
-    if (t >= 6 * lg.lx) return;
-    const int x = t % lg.lx, wr = t / lg.lx;
-    const int wall = wr / 3, r = wr % 3;
-    const int y = wall == 0 ? r : lg.ly - 1 - r;
-    const int yg = wall == 0 ? -r - 1 : lg.ly + r;
-    double* col = lam + lg.origin + (long long)x * lg.cs;
-    double gh[NPOP], in[NPOP];
+    __shared__ double part[BCF_COLS][3][NPOP];
+    const int wall = blockIdx.y;
+    const int t = threadIdx.x;
+    const int cj = t / NPOP, l = t - cj * NPOP;
+    const int x = blockIdx.x * BCF_COLS + cj;
+    const bool act = t < BCF_COLS * NPOP && x < lg.lx;
+    L* seg = nullptr;
+    double in[3] = {0.0, 0.0, 0.0};
+    if (act) {
+        const int ey = c_hops.ey[l];
+        const int en = wall == 0 ? ey : -ey;
+        const double ew = wt->ew[wall][l];
+        seg = lam + (size_t)l * lg.ps + lg.origin + (long long)x * lg.cs;
 #pragma unroll
-    for (int l = 0; l < NPOP; ++l) {
-        const int en = wall == 0 ? EY[l] : -EY[l];
-        gh[l] = (en >= r + 1) ? col[(size_t)l * lg.ps + yg] : 0.0;
-        in[l] = (-en > r) ? 0.0 : col[(size_t)l * lg.ps + y];
+        for (int r = 0; r < 3; ++r) {
+            const int y = wall == 0 ? r : lg.ly - 1 - r;
+            const int yg = wall == 0 ? -r - 1 : lg.ly + r;
+            part[cj][r][l] = (en >= r + 1) ? ew * (double)seg[yg] : 0.0;
+            in[r] = (-en > r) ? 0.0 : (double)seg[y];
+        }
     }
-    double beta = 0.0;
+    __syncthreads();
+    if (act) {
 #pragma unroll
-    for (int l = 0; l < NPOP; ++l) beta += wt.ew[wall][l] * gh[l];
-#pragma unroll
-    for (int l = 0; l < NPOP; ++l) col[(size_t)l * lg.ps + y] = in[l] + beta;
+        for (int r = 0; r < 3; ++r) {
+            double beta = 0.0;
+            for (int k = 0; k < NPOP; ++k) beta += part[cj][r][k];
+            const int y = wall == 0 ? r : lg.ly - 1 - r;
+            seg[y] = (L)(in[r] + beta);
+        }
+    }
 }
 
 // lambda_l = d(x,y) dT/df_l = d (|xi_l - u|^2 - 2T) / (2 rho), with
 // d = dT(x,y) (SEED) or d = T - T_target (LOSS, plus 1/2 d^2 into partials).
-template <typename S, bool LOSS>
-__global__ __launch_bounds__(SITE_THREADS) void k_adj_seed_T(const S* __restrict__ fbuf, Geo g, double* __restrict__ lam, Geo lg,
+template <typename S, typename L, bool LOSS>
+__global__ __launch_bounds__(SITE_THREADS) void k_adj_seed_T(const S* __restrict__ fbuf, Geo g, L* __restrict__ lam, Geo lg,
                                                           const double* __restrict__ d_in, double* __restrict__ partials)
 {
-    const int x = blockIdx.y;
-    const int y = blockIdx.x * SITE_THREADS + threadIdx.x;
+    const SiteBlock sb = site_block(g);
+    const int x = sb.x, y = sb.y;
     double loss = 0.0;
     if (y < g.ly) {
         double rho, ux, uy, T;
@@ -249,11 +267,11 @@ __global__ __launch_bounds__(SITE_THREADS) void k_adj_seed_T(const S* __restrict
         double d = d_in[(long long)x * g.ly + y];
         if (LOSS) { d = T - d; loss = 0.5 * d * d; }
         const double k = d / (2.0 * rho);
-        double* lp = lam + lg.origin + (long long)x * lg.cs + y;
+        L* lp = lam + lg.origin + (long long)x * lg.cs + y;
 #pragma unroll
         for (int l = 0; l < NPOP; ++l) {
             const double dx = C * EX[l] - ux, dy = C * EY[l] - uy;
-            lp[(size_t)l * lg.ps] = k * (dx * dx + dy * dy - 2.0 * T);
+            lp[(size_t)l * lg.ps] = (L)(k * (dx * dx + dy * dy - 2.0 * T));
         }
     }
     if (LOSS) block_sum1(loss, partials);
@@ -262,12 +280,13 @@ __global__ __launch_bounds__(SITE_THREADS) void k_adj_seed_T(const S* __restrict
 // dL/dP from lambda_0 for f_0 = f^eq(rho0(P), 0, T0(P)):
 //   T0 = t_mid - t_amp tanh(z), z = (y - y_mid - P) / width, rho0 = p0 / T0,
 //   f^eq_l(rho, 0, T) = w_l rho (1 + th K1 + th^2 K3), th = T - 1.
-__global__ __launch_bounds__(SITE_THREADS) void k_adj_init_rt(const double* __restrict__ lam, Geo lg, const double* __restrict__ P,
+template <typename L>
+__global__ __launch_bounds__(SITE_THREADS) void k_adj_init_rt(const L* __restrict__ lam, Geo lg, const double* __restrict__ P,
                                                            RtProfile pr, double* __restrict__ dP)
 {
     using K = ShellK<double>;
-    const int x = blockIdx.y;
-    const int y = blockIdx.x * SITE_THREADS + threadIdx.x;
+    const SiteBlock sb = site_block(lg);
+    const int x = sb.x, y = sb.y;
     if (y >= lg.ly) return;
     const long long s = (long long)x * lg.ly + y;
     const double th_z = tanh((y - pr.y_mid - P[s]) / pr.width);
@@ -276,16 +295,29 @@ __global__ __launch_bounds__(SITE_THREADS) void k_adj_init_rt(const double* __re
     const double dT = pr.t_amp * (1.0 - th_z * th_z) / pr.width;
     const double dr = -pr.p0 / (T0 * T0) * dT;
     const double th = T0 - 1.0;
-    const double* lp = lam + lg.origin + (long long)x * lg.cs + y;
+    const L* lp = lam + lg.origin + (long long)x * lg.cs + y;
     double acc = 0.0;
 #pragma unroll
     for (int l = 0; l < NPOP; ++l) {
         const int sh = SHELL[l];
         const double Pl = 1.0 + th * (K::k1(sh) + th * K::k3(sh));
         const double dPl = K::k1(sh) + 2.0 * th * K::k3(sh);
-        acc += lp[(size_t)l * lg.ps] * W_SHELL[sh] * (Pl * dr + r0 * dPl * dT);
+        acc += (double)lp[(size_t)l * lg.ps] * W_SHELL[sh] * (Pl * dr + r0 * dPl * dT);
     }
     dP[s] = acc;
+}
+
+// lambda canonical FP64 [37][lx][ly] <-> padded buffer of type L
+template <typename L, bool TO_CANON>
+__global__ __launch_bounds__(256) void k_lambda_canon(L* __restrict__ buf, double* __restrict__ canon, Geo g)
+{
+    const int l = blockIdx.z, x = blockIdx.y;
+    const int y = blockIdx.x * 256 + threadIdx.x;
+    if (y >= g.ly) return;
+    const size_t pi = (size_t)l * g.ps + g.origin + (long long)x * g.cs + y;
+    const size_t ci = ((size_t)l * g.lx + x) * g.ly + y;
+    if (TO_CANON) canon[ci] = (double)buf[pi];
+    else buf[pi] = (L)canon[ci];
 }
 
 }  // namespace lbm

@@ -24,9 +24,12 @@ struct Plan {
     Geo geo;          // population buffers, storage precision
     Geo lgeo;         // adjoint lambda buffers, FP64
     size_t elem;      // bytes per stored population value
-    size_t state_bytes;
+    size_t buf_bytes; // one population buffer
+    size_t wall_bytes;// one wall-density table (6 * lx doubles)
+    size_t state_bytes; // snapshot: population buffer + its wall densities
     size_t off_buf[2];
     size_t off_wall;  // 2 x 6 * lx doubles (double-buffered wall densities)
+    size_t off_tab;   // device copy of the wall table (E^w, w)
     size_t off_part;  // RED_BLOCKS * 4 doubles, then 2 doubles of loss/dtau scratch
     size_t off_lam[2];
     size_t off_apart; // adjoint: one double per collide block
@@ -65,6 +68,7 @@ bool valid(const lbm_params* p)
     if (p->xmode != LBM_X_WRAP && p->xmode != LBM_X_HALO) return false;
     if (p->step_kind != LBM_STEP_SPLIT && p->step_kind != LBM_STEP_FUSED) return false;
     if (p->layout != LBM_LAYOUT_PLANES && p->layout != LBM_LAYOUT_COLUMNS) return false;
+    if (p->adjoint < 0 || p->adjoint > 2) return false;
     if ((long long)p->lx * p->ly > (1LL << 31)) return false;
     return true;
 }
@@ -74,15 +78,18 @@ Plan plan(const lbm_params* p)
     Plan pl{};
     pl.elem = p->precision == LBM_FP64 ? 8 : 4;
     pl.geo = make_geo(p->lx, p->ly, pl.elem, p->layout);
-    pl.lgeo = make_geo(p->lx, p->ly, 8, p->layout);
-    pl.state_bytes = align_up((size_t)pl.geo.total * pl.elem, ALIGN);
+    pl.lgeo = make_geo(p->lx, p->ly, p->adjoint == 2 ? 4 : 8, p->layout);
+    pl.buf_bytes = align_up((size_t)pl.geo.total * pl.elem, ALIGN);
+    pl.wall_bytes = align_up(6 * (size_t)p->lx * 8, ALIGN);
+    pl.state_bytes = pl.buf_bytes + pl.wall_bytes;
     size_t off = 0;
-    pl.off_buf[0] = off; off += pl.state_bytes;
-    pl.off_buf[1] = off; off += pl.state_bytes;
-    pl.off_wall = off; off += 2 * align_up(6 * (size_t)p->lx * 8, ALIGN);
+    pl.off_buf[0] = off; off += pl.buf_bytes;
+    pl.off_buf[1] = off; off += pl.buf_bytes;
+    pl.off_wall = off; off += 2 * pl.wall_bytes;
+    pl.off_tab = off; off += align_up(sizeof(WallTable), ALIGN);
     pl.off_part = off; off += align_up(((size_t)RED_BLOCKS * 4 + 2) * 8, ALIGN);
     if (p->adjoint) {
-        const size_t lb = align_up((size_t)pl.lgeo.total * 8, ALIGN);
+        const size_t lb = align_up((size_t)pl.lgeo.total * (p->adjoint == 2 ? 4 : 8), ALIGN);
         pl.off_lam[0] = off; off += lb;
         pl.off_lam[1] = off; off += lb;
         const size_t nb = (size_t)((p->ly + SITE_THREADS - 1) / SITE_THREADS) * p->lx;
@@ -115,11 +122,13 @@ struct lbm_ctx {
     std::string err;
 
     void* buf(int i) { return ws + pl.off_buf[i]; }
-    double* wall_rho(int i) { return reinterpret_cast<double*>(ws + pl.off_wall + i * align_up(6 * (size_t)p.lx * 8, ALIGN)); }
+    double* wall_rho(int i) { return reinterpret_cast<double*>(ws + pl.off_wall + i * pl.wall_bytes); }
+    const WallTable* dev_tables() { return reinterpret_cast<const WallTable*>(ws + pl.off_tab); }
     double* partials() { return reinterpret_cast<double*>(ws + pl.off_part); }
     double* scratch2() { return partials() + (size_t)RED_BLOCKS * 4; }
-    double* lam(int i) { return reinterpret_cast<double*>(ws + pl.off_lam[i]); }
+    template <typename L> L* lam(int i) { return reinterpret_cast<L*>(ws + pl.off_lam[i]); }
     bool fp64() const { return p.precision == LBM_FP64; }
+    bool lam32() const { return p.adjoint == 2; }
 };
 
 namespace {
@@ -153,7 +162,8 @@ void set_collide_args(lbm_ctx* c)
     c->cargs.grav_th_f = (float)c->cargs.grav_th;
 }
 
-dim3 site_grid(const Geo& g) { return dim3((g.ly + SITE_THREADS - 1) / SITE_THREADS, g.lx, 1); }
+// 1-D grid of site blocks, renumbered per XCD inside the kernels (site_block)
+dim3 site_grid(const Geo& g) { return dim3((unsigned)((g.ly + SITE_THREADS - 1) / SITE_THREADS) * (unsigned)g.lx); }
 
 template <typename S>
 lbm_status launch_propagate(lbm_ctx* c, const S* src, S* dst)
@@ -309,6 +319,11 @@ lbm_status do_step(lbm_ctx* c, int64_t n)
 }
 
 #define DISPATCH(c, fn, ...) ((c)->fp64() ? fn<double>(c, ##__VA_ARGS__) : fn<float>(c, ##__VA_ARGS__))
+// storage type S and adjoint-state type L
+#define ADJ_DISPATCH(c, fn, ...)                                                                \
+    ((c)->fp64() ? ((c)->lam32() ? fn<double, float>(c, ##__VA_ARGS__) : fn<double, double>(c, ##__VA_ARGS__)) \
+                 : ((c)->lam32() ? fn<float, float>(c, ##__VA_ARGS__) : fn<float, double>(c, ##__VA_ARGS__)))
+#define LAM_DISPATCH(c, fn, ...) ((c)->lam32() ? fn<float>(c, ##__VA_ARGS__) : fn<double>(c, ##__VA_ARGS__))
 
 template <typename S>
 lbm_status do_init(lbm_ctx* c, const double* rho, const double* ux, const double* uy, const double* T)
@@ -350,6 +365,22 @@ lbm_status do_canon(lbm_ctx* c, void* canon, bool to_canon)
     }
     return check_launch(c, "canonical copy");
 }
+// snapshot = current population buffer + its wall densities (walls only)
+template <typename S>
+lbm_status do_get_state(lbm_ctx* c, char* dst)
+{
+    if (hipMemcpyAsync(dst, c->buf(c->cur), c->pl.buf_bytes, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+        return check_launch(c, "get_state");
+    if (c->p.ybc == LBM_Y_WALLS) {
+        lbm_status s = ensure_wall_density<S>(c, c->cur);
+        if (s) return s;
+        if (hipMemcpyAsync(dst + c->pl.buf_bytes, c->wall_rho(c->wr_cur), c->pl.wall_bytes, hipMemcpyDeviceToDevice,
+                           c->stream) != hipSuccess)
+            return check_launch(c, "get_state");
+    }
+    return LBM_OK;
+}
+
 template <typename S>
 lbm_status do_conservation(lbm_ctx* c, double* out4)
 {
@@ -398,8 +429,10 @@ lbm_status lbm_create(const lbm_params* p, void* dev_workspace, size_t bytes, vo
         c->wt.w[l] = W_SHELL[SHELL[l]];
     }
     set_collide_args(c);
-    if (hipMemsetAsync(dev_workspace, 0, pl.total, c->stream) != hipSuccess) {
-        g_create_error = "hipMemsetAsync of the workspace failed";
+    if (hipMemsetAsync(dev_workspace, 0, pl.total, c->stream) != hipSuccess ||
+        hipMemcpyAsync(c->ws + pl.off_tab, &c->wt, sizeof(WallTable), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess) {
+        g_create_error = "workspace initialisation failed";
         delete c;
         return LBM_ERR_HIP;
     }
@@ -485,19 +518,24 @@ lbm_status lbm_get_state(lbm_ctx* c, void* dst)
 {
     if (!c) return LBM_ERR_INVALID;
     if (!dst) return fail(c, LBM_ERR_INVALID, "get_state: NULL");
-    if (hipMemcpyAsync(dst, c->buf(c->cur), c->pl.state_bytes, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
-        return check_launch(c, "get_state");
-    return LBM_OK;
+    return DISPATCH(c, do_get_state, (char*)dst);
 }
 
 lbm_status lbm_set_state(lbm_ctx* c, const void* src)
 {
     if (!c) return LBM_ERR_INVALID;
     if (!src) return fail(c, LBM_ERR_INVALID, "set_state: NULL");
-    if (hipMemcpyAsync(c->buf(c->cur), src, c->pl.state_bytes, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+    const char* s = (const char*)src;
+    if (hipMemcpyAsync(c->buf(c->cur), s, c->pl.buf_bytes, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
         return check_launch(c, "set_state");
     c->have_prev = false;
     c->wr_buf = -1;
+    if (c->p.ybc == LBM_Y_WALLS) {
+        if (hipMemcpyAsync(c->wall_rho(c->wr_cur), s + c->pl.buf_bytes, c->pl.wall_bytes, hipMemcpyDeviceToDevice,
+                           c->stream) != hipSuccess)
+            return check_launch(c, "set_state");
+        c->wr_buf = c->cur;
+    }
     return LBM_OK;
 }
 

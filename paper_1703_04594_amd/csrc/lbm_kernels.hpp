@@ -72,6 +72,30 @@ __device__ __forceinline__ int wrap_x(int xs, int lx)
     return xs < 0 ? xs + lx : (xs >= lx ? xs - lx : xs);
 }
 
+// Workgroups are dispatched to the 8 XCDs (each with its own L2) round-robin by
+// linear id.  Site kernels use a 1-D grid and renumber hardware block b as
+// L = k q + min(k, r) + i  (k = b mod 8, i = b div 8, N = 8 q + r blocks), a
+// bijection that hands each XCD one contiguous run of lattice chunks, so the
+// cache lines shared by neighbouring chunks (shifted gathers and pushes) are
+// reused in the same L2.
+constexpr int NXCD = 8;
+constexpr int SITE_THREADS = 256;
+__device__ __forceinline__ int xcd_block(int b, int n)
+{
+    const int k = b % NXCD, i = b / NXCD;
+    const int q = n / NXCD, r = n % NXCD;
+    return k * q + (k < r ? k : r) + i;
+}
+
+// Site kernels: block L covers sites y in [bx * SITE_THREADS, ...) of column x.
+struct SiteBlock { int x, y; };
+__device__ __forceinline__ SiteBlock site_block(const Geo& g)
+{
+    const int nyb = (g.ly + SITE_THREADS - 1) / SITE_THREADS;
+    const int L = xcd_block(blockIdx.x, nyb * g.lx);
+    return SiteBlock{L / nyb, (L % nyb) * SITE_THREADS + (int)threadIdx.x};
+}
+
 // Plane access as (block-uniform base pointer) + (per-thread 32-bit byte
 // offset): the base lives in scalar registers and one vector offset serves all
 // 37 planes, so no 64-bit per-plane vector addresses are kept alive.
@@ -201,7 +225,6 @@ __global__ __launch_bounds__(256) void k_bc_apply(S* __restrict__ dst, Geo g, co
 // ---------------------------------------------------------------------------
 // collide: one thread per site, in place.
 // ---------------------------------------------------------------------------
-constexpr int SITE_THREADS = 256;
 
 // Density of a site from its just-written populations, summed in population
 // order in FP64 exactly as k_wall_density sums them, into the wall-density
@@ -224,8 +247,8 @@ __global__ __launch_bounds__(SITE_THREADS) void k_collide(S* __restrict__ buf, G
                                                        double* __restrict__ wall_rho_out)
 {
     using Cc = typename Store<S>::C;
-    const int x = blockIdx.y;
-    const int y = blockIdx.x * SITE_THREADS + threadIdx.x;
+    const SiteBlock sb = site_block(g);
+    const int x = sb.x, y = sb.y;
     if (y >= g.ly) return;
     S* col = buf + g.origin + (long long)x * g.cs;
     const unsigned yb = (unsigned)y * (unsigned)sizeof(S);
@@ -247,8 +270,8 @@ __global__ __launch_bounds__(SITE_THREADS) void k_step_fused(const S* __restrict
                                                           double* __restrict__ wall_rho_out)
 {
     using Cc = typename Store<S>::C;
-    const int x = blockIdx.y;
-    const int y = blockIdx.x * SITE_THREADS + threadIdx.x;
+    const SiteBlock sb = site_block(g);
+    const int x = sb.x, y = sb.y;
     if (y >= g.ly) return;
     const unsigned yb = (unsigned)y * (unsigned)sizeof(S);
     Cc f[NPOP];
@@ -288,8 +311,8 @@ __global__ __launch_bounds__(SITE_THREADS) void k_init_fields(S* __restrict__ bu
                                                            const double* __restrict__ ux, const double* __restrict__ uy,
                                                            const double* __restrict__ T)
 {
-    const int x = blockIdx.y;
-    const int y = blockIdx.x * SITE_THREADS + threadIdx.x;
+    const SiteBlock sb = site_block(g);
+    const int x = sb.x, y = sb.y;
     if (y >= g.ly) return;
     const long long s = (long long)x * g.ly + y;
     const double r = rho[s], vx = ux[s], vy = uy[s], t = T[s];
@@ -303,8 +326,8 @@ struct RtProfile { double t_mid, t_amp, p0, width, y_mid; };
 template <typename S>
 __global__ __launch_bounds__(SITE_THREADS) void k_init_rt(S* __restrict__ buf, Geo g, const double* __restrict__ P, RtProfile pr)
 {
-    const int x = blockIdx.y;
-    const int y = blockIdx.x * SITE_THREADS + threadIdx.x;
+    const SiteBlock sb = site_block(g);
+    const int x = sb.x, y = sb.y;
     if (y >= g.ly) return;
     const double T0 = pr.t_mid - pr.t_amp * tanh((y - pr.y_mid - P[(long long)x * g.ly + y]) / pr.width);
     const double r0 = pr.p0 / T0;
@@ -340,8 +363,8 @@ template <typename S>
 __global__ __launch_bounds__(SITE_THREADS) void k_macros(const S* __restrict__ buf, Geo g, double* __restrict__ rho,
                                                       double* __restrict__ ux, double* __restrict__ uy, double* __restrict__ T)
 {
-    const int x = blockIdx.y;
-    const int y = blockIdx.x * SITE_THREADS + threadIdx.x;
+    const SiteBlock sb = site_block(g);
+    const int x = sb.x, y = sb.y;
     if (y >= g.ly) return;
     double r, vx, vy, t;
     site_macros<S>(buf + g.origin + (long long)x * g.cs + y, g.ps, r, vx, vy, t);

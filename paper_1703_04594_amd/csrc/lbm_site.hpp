@@ -135,34 +135,35 @@ __device__ __forceinline__ void collide_site(C (&f)[NPOP], const CollideArgs& ar
     const C b1 = C(1) - C(0.5) * u2;             // A1 without th
     const C b2 = C(0.5) - C(0.25) * u2;          // A2 without th
     const C b0m1 = u2 * (C(-0.5) + C(0.125) * u2); // A0 - 1 without th
-    C A0m1[NSHELL], A1[NSHELL], A2[NSHELL];
+    // populations are ordered by shell: form each shell's coefficients just
+    // before its populations, so only one shell's worth is live
 #pragma unroll
     for (int s = 0; s < NSHELL; ++s) {
-        A0m1[s] = b0m1 + th * (K::k1(s) + u2 * K::k2(s) + th * K::k3(s));
-        A1[s] = b1 + th * K::k4(s);
-        A2[s] = b2 + th * K::k5(s);
-    }
+        const C A0m1 = b0m1 + th * (K::k1(s) + u2 * K::k2(s) + th * K::k3(s));
+        const C A1 = b1 + th * K::k4(s);
+        const C A2 = b2 + th * K::k5(s);
 #pragma unroll
-    for (int l = 0; l < NPOP; ++l) {
-        const int s = SHELL[l];
-        C pm;   // P - 1 = A0 - 1 + a (A1 + a (A2 + a (1/6 + a/24)))
-        if (l == 0) {
-            pm = A0m1[0];
-        } else {
-            const C a = hop_dot<C>(l, cux, cuy);
-            C t = a * C(1.0 / 24.0) + C(1.0 / 6.0);
-            t = t * a + A2[s];
-            t = t * a + A1[s];
-            pm = t * a + A0m1[s];
+        for (int l = 0; l < NPOP; ++l) {
+            if (SHELL[l] != s) continue;
+            C pm;   // P - 1 = A0 - 1 + a (A1 + a (A2 + a (1/6 + a/24)))
+            if (l == 0) {
+                pm = A0m1;
+            } else {
+                const C a = hop_dot<C>(l, cux, cuy);
+                C t = a * C(1.0 / 24.0) + C(1.0 / 6.0);
+                t = t * a + A2;
+                t = t * a + A1;
+                pm = t * a + A0m1;
+            }
+            C feq;
+            if constexpr (SHIFTED) {
+                // d^eq = w ((rho - 1) P + (P - 1)) = w (m0 + rho (P - 1))
+                feq = wshell<C>(s) * (m0 + rho * pm);
+            } else {
+                feq = wshell<C>(s) * rho * (C(1) + pm);
+            }
+            f[l] = f[l] + omega * (feq - f[l]);
         }
-        C feq;
-        if constexpr (SHIFTED) {
-            // d^eq = w ((rho - 1) P + (P - 1)) = w (m0 + rho (P - 1))
-            feq = wshell<C>(s) * (m0 + rho * pm);
-        } else {
-            feq = wshell<C>(s) * rho * (C(1) + pm);
-        }
-        f[l] = f[l] + omega * (feq - f[l]);
     }
     if constexpr (SHIFTED) {
         const C g = arg_g<C>(args);

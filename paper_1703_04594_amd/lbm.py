@@ -130,9 +130,13 @@ def scale_c() -> float:
     return float(lib().lbm_scale_c())
 
 
+_ADJ = {False: 0, None: 0, 0: 0, True: 1, 1: 1, "fp64": 1, 2: 2, "fp32": 2}
+
+
 def make_params(lx, ly, tau, g_y=0.0, t_bottom=1.0, t_top=1.0, precision="fp64", ybc="walls",
                 xmode="wrap", step="split", adjoint=False, layout="columns") -> Params:
-    return Params(lx, ly, _PREC[precision], _YBC[ybc], _XMODE[xmode], _STEP[step], int(bool(adjoint)),
+    """adjoint: False (none), True / "fp64" (FP64 lambda) or "fp32" (FP32 lambda storage)."""
+    return Params(lx, ly, _PREC[precision], _YBC[ybc], _XMODE[xmode], _STEP[step], _ADJ[adjoint],
                   _LAYOUT[layout], tau, g_y, t_bottom, t_top)
 
 

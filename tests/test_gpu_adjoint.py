@@ -100,6 +100,34 @@ def test_temperature_seed_loss_and_init_transpose(precision):
     assert rel(dP, Pv.grad) <= 1e-12
 
 
+@pytest.mark.parametrize("ybc", ["walls", "periodic"])
+@pytest.mark.parametrize("layout", ["columns", "planes"])
+def test_one_reverse_step_with_fp32_lambda(ybc, layout):
+    """FP32 lambda storage: the same reverse step, with lambda_{n+1} rounded to
+    FP32 on both sides; only the stored output is rounded, so lambda_n agrees
+    to FP32 rounding and d/dtau (accumulated in FP64) to 1e-12."""
+    lx, ly, g = 24, 20, -1e-3
+    say(f"adjoint step fp32 lambda {ybc} {layout}")
+    noise = torch.tensor(inputs.population_noise(lx, ly, 31))
+    lam1 = torch.tensor(inputs.population_noise(lx, ly, 32)).float().double()
+    lat = Lattice(lx, ly, TAU, g, TB, TT, precision="fp32", ybc=ybc, adjoint="fp32", layout=layout, device=DEV)
+    f_store = (WT[:, None, None] * 0.05 * noise).to(torch.float32)
+    f64 = WT[:, None, None] + f_store.to(torch.float64)
+    lat.set_pops(f_store.to(DEV))
+    st = lat.get_state()
+    lat.set_lambda(lam1.to(DEV))
+    dacc = torch.zeros((), dtype=torch.float64, device=DEV)
+    lat.adjoint_step(st, dacc)
+    lam0 = lat.get_lambda()
+    m = TorchD2Q37(lx, ly, g, TB, TT, walls=(ybc == "walls"))
+    f = f64.clone().requires_grad_(True)
+    tau = torch.tensor(TAU, dtype=torch.float64, requires_grad=True)
+    (m.step(f, tau) * lam1).sum().backward()
+    e_lam, e_tau = rel(lam0, f.grad), rel(dacc, tau.grad)
+    say(f"  lambda {e_lam:.2e}  dtau {e_tau:.2e}")
+    assert e_lam <= 2e-7 and e_tau <= 1e-12
+
+
 @pytest.mark.parametrize("schedule", ["sqrt", "binomial"])
 @pytest.mark.parametrize("ybc_g", [-2e-3])
 def test_rollout_gradient_matches_autograd(schedule, ybc_g):
@@ -154,12 +182,14 @@ def test_512x512_gradient_against_central_differences():
         del lat
     Tt = targets["fp64"]
     grads = {}
-    for prec in ("fp64", "fp32"):
-        cfg = RolloutConfig(lx, ly, n, precision=prec, checkpoint="sqrt")
+    for prec in ("fp64", "fp32", "fp32/fp32-lambda"):
+        fwd = prec.split("/")[0]
+        cfg = RolloutConfig(lx, ly, n, precision=fwd, checkpoint="sqrt",
+                            lambda_precision="fp32" if "lambda" in prec else "fp64")
         Pg = P.clone().requires_grad_(True)
         tg = torch.tensor(TAU, dtype=torch.float64, device=DEV, requires_grad=True)
         T = rt_temperature(Pg, tg, cfg)
-        (0.5 * ((T - targets[prec]) ** 2).sum()).backward()
+        (0.5 * ((T - targets[fwd]) ** 2).sum()).backward()
         grads[prec] = (Pg.grad.clone(), float(tg.grad))
         say(f"  {prec} stats {cfg.stats}")
     gP, gtau = grads["fp64"]
@@ -199,6 +229,10 @@ def test_512x512_gradient_against_central_differences():
     # while T_N - T* (the adjoint seed) is only ~1e-4; this guards against a
     # broken FP32 adjoint path
     assert e32 <= 0.5
+    g3, t3 = grads["fp32/fp32-lambda"]
+    e3 = float((g3 - g32).norm() / g32.norm())
+    say(f"  FP32 lambda vs FP64 lambda (same FP32 forward): rel L2 {e3:.2e}, dtau {abs(t3 - t32) / abs(t32):.2e}")
+    assert e3 <= 1e-3
 
 
 def test_binomial_and_sqrt_give_bitwise_equal_gradients():
