@@ -328,7 +328,8 @@ def cpu_baseline(args, budget_s=15.0):
 def profile_workload(args):
     """Short fixed sequence for rocprofv3 runs: a plain device copy of known
     size (calibrates the HBM byte counters), then FP64 and FP32 fused steps,
-    the FP64 split kernels and FP32 adjoint steps on the bench lattice."""
+    FP64 and FP32 split steps, and adjoint steps over FP32 states with FP64
+    and FP32 lambda, all on the bench lattice."""
     import torch
 
     from paper_1703_04594_amd import inputs
@@ -349,20 +350,23 @@ def profile_workload(args):
         lat.step(args.steps)
         torch.cuda.synchronize()
         del lat
-    lat = Lattice(lx, ly, 0.7, -1e-5, 4 / 3, 2 / 3, precision="fp64", step="split", device=dev)
-    lat.init_rt(P)
-    lat.step(args.steps)
-    torch.cuda.synchronize()
-    del lat
-    lat = Lattice(lx, ly, 0.7, -1e-5, 4 / 3, 2 / 3, precision="fp32", step="fused", adjoint=True, device=dev)
-    lat.init_rt(P)
-    st = lat.get_state()
-    lat.step(1)
-    lat.seed_temperature(torch.ones((lx, ly), dtype=torch.float64, device=dev))
-    dacc = torch.zeros((), dtype=torch.float64, device=dev)
-    for _ in range(args.steps):
-        lat.adjoint_step(st, dacc)
-    torch.cuda.synchronize()
+    for prec in ("fp64", "fp32"):
+        lat = Lattice(lx, ly, 0.7, -1e-5, 4 / 3, 2 / 3, precision=prec, step="split", device=dev)
+        lat.init_rt(P)
+        lat.step(args.steps)
+        torch.cuda.synchronize()
+        del lat
+    for lam in ("fp64", "fp32"):
+        lat = Lattice(lx, ly, 0.7, -1e-5, 4 / 3, 2 / 3, precision="fp32", step="fused", adjoint=lam, device=dev)
+        lat.init_rt(P)
+        st = lat.get_state()
+        lat.step(1)
+        lat.seed_temperature(torch.ones((lx, ly), dtype=torch.float64, device=dev))
+        dacc = torch.zeros((), dtype=torch.float64, device=dev)
+        for _ in range(args.steps):
+            lat.adjoint_step(st, dacc)
+        torch.cuda.synchronize()
+        del lat, st
     print(json.dumps({"profile_workload": "done", "steps": args.steps}), flush=True)
 
 

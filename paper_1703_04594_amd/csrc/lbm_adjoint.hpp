@@ -125,7 +125,7 @@ __device__ __forceinline__ double adjoint_site(double m0, double sx, double sy, 
 __device__ __forceinline__ void block_sum1(double v, double* __restrict__ partials)
 {
     double a[1] = {v};
-    block_sum_store<1>(a, partials + (size_t)blockIdx.y * gridDim.x + blockIdx.x);
+    block_sum_store<1, SITE_THREADS>(a, partials + (size_t)blockIdx.y * gridDim.x + blockIdx.x);
 }
 
 template <typename S, typename L, bool WALLS>

@@ -170,13 +170,20 @@ lbm_status launch_propagate(lbm_ctx* c, const S* src, S* dst)
 {
     const Geo& g = c->pl.geo;
     constexpr int VEC = sizeof(S) == 8 ? 2 : 4;
-    constexpr int UNROLL = 4;
+    constexpr int UNROLL = PROP_UNROLL;
     constexpr int CH = PROP_THREADS * VEC * UNROLL;
-    dim3 grid((g.ly + CH - 1) / CH, g.lx, NPOP);
-    if (c->p.xmode == LBM_X_WRAP)
-        hipLaunchKernelGGL((k_propagate<S, VEC, UNROLL, true>), grid, dim3(PROP_THREADS), 0, c->stream, src, dst, g);
+    const unsigned nch = (unsigned)((g.ly + CH - 1) / CH);
+    const bool cols = c->p.layout == LBM_LAYOUT_COLUMNS;
+    const dim3 grid = cols ? dim3(nch, NPOP, g.lx) : dim3(nch, g.lx, NPOP);
+    const bool wrap = c->p.xmode == LBM_X_WRAP;
+    if (wrap && cols)
+        hipLaunchKernelGGL((k_propagate<S, VEC, UNROLL, true, true>), grid, dim3(PROP_THREADS), 0, c->stream, src, dst, g);
+    else if (wrap)
+        hipLaunchKernelGGL((k_propagate<S, VEC, UNROLL, true, false>), grid, dim3(PROP_THREADS), 0, c->stream, src, dst, g);
+    else if (cols)
+        hipLaunchKernelGGL((k_propagate<S, VEC, UNROLL, false, true>), grid, dim3(PROP_THREADS), 0, c->stream, src, dst, g);
     else
-        hipLaunchKernelGGL((k_propagate<S, VEC, UNROLL, false>), grid, dim3(PROP_THREADS), 0, c->stream, src, dst, g);
+        hipLaunchKernelGGL((k_propagate<S, VEC, UNROLL, false, false>), grid, dim3(PROP_THREADS), 0, c->stream, src, dst, g);
     return check_launch(c, "propagate");
 }
 

@@ -88,11 +88,15 @@ __device__ __forceinline__ int xcd_block(int b, int n)
 }
 
 // Site kernels: block L covers sites y in [bx * SITE_THREADS, ...) of column x.
+// (Measured: the renumbering gains 5% on the FP64 step and 14% on the
+// adjoint step, but costs ~1% on the FP32 step, which therefore keeps the
+// hardware order.)
 struct SiteBlock { int x, y; };
+template <bool REMAP = true>
 __device__ __forceinline__ SiteBlock site_block(const Geo& g)
 {
     const int nyb = (g.ly + SITE_THREADS - 1) / SITE_THREADS;
-    const int L = xcd_block(blockIdx.x, nyb * g.lx);
+    const int L = REMAP ? xcd_block(blockIdx.x, nyb * g.lx) : (int)blockIdx.x;
     return SiteBlock{L / nyb, (L % nyb) * SITE_THREADS + (int)threadIdx.x};
 }
 
@@ -132,15 +136,23 @@ template <> struct VecA<double, 2> { typedef double T __attribute__((ext_vector_
 template <> struct VecA<float, 2> { typedef float T __attribute__((ext_vector_type(2))); };
 template <> struct VecA<float, 4> { typedef float T __attribute__((ext_vector_type(4))); };
 
-constexpr int PROP_THREADS = 256;
+// propagate: 128 threads, one 16-byte vector each, so a block moves 2 KB of one
+// segment.  Measured on the 2048x4096 lattice: 2 KB blocks beat 1, 4, 8 and
+// 16 KB ones, and the hardware block order (all XCDs sweeping the same region
+// of memory together) beats an XCD-contiguous renumbering.
+constexpr int PROP_THREADS = 128;
+constexpr int PROP_UNROLL = 1;
 
-template <typename S, int VEC, int UNROLL, bool WRAP>
+// Blocks are numbered so that consecutive blocks stream consecutive memory:
+// chunk fastest, then the population index (COLS layout: the 37 segments of a
+// column are contiguous) or the column (planes layout).
+template <typename S, int VEC, int UNROLL, bool WRAP, bool COLS>
 __global__ __launch_bounds__(PROP_THREADS) void k_propagate(const S* __restrict__ src, S* __restrict__ dst, Geo g)
 {
     using VU = typename VecT<S, VEC>::T;
     using VA = typename VecA<S, VEC>::T;
-    const int l = blockIdx.z;
-    const int x = blockIdx.y;
+    const int l = COLS ? blockIdx.y : blockIdx.z;
+    const int x = COLS ? blockIdx.z : blockIdx.y;
     const int ex = c_hops.ex[l], ey = c_hops.ey[l];
     int xs = x - ex;
     if (WRAP) xs = wrap_x(xs, g.lx);
@@ -247,7 +259,7 @@ __global__ __launch_bounds__(SITE_THREADS) void k_collide(S* __restrict__ buf, G
                                                        double* __restrict__ wall_rho_out)
 {
     using Cc = typename Store<S>::C;
-    const SiteBlock sb = site_block(g);
+    const SiteBlock sb = site_block<sizeof(S) == 8>(g);
     const int x = sb.x, y = sb.y;
     if (y >= g.ly) return;
     S* col = buf + g.origin + (long long)x * g.cs;
@@ -270,7 +282,7 @@ __global__ __launch_bounds__(SITE_THREADS) void k_step_fused(const S* __restrict
                                                           double* __restrict__ wall_rho_out)
 {
     using Cc = typename Store<S>::C;
-    const SiteBlock sb = site_block(g);
+    const SiteBlock sb = site_block<sizeof(S) == 8>(g);
     const int x = sb.x, y = sb.y;
     if (y >= g.ly) return;
     const unsigned yb = (unsigned)y * (unsigned)sizeof(S);
@@ -396,10 +408,12 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-template <int N>
+// Sum of v over a block of NT threads (NT a multiple of 64), written to out.
+template <int N, int NT>
 __device__ __forceinline__ void block_sum_store(double (&v)[N], double* __restrict__ out)
 {
-    __shared__ double red[N][256 / 64];
+    static_assert(NT % 64 == 0, "whole wavefronts");
+    __shared__ double red[N][NT / 64];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
     for (int i = 0; i < N; ++i) {
@@ -409,7 +423,7 @@ __device__ __forceinline__ void block_sum_store(double (&v)[N], double* __restri
     __syncthreads();
     if (threadIdx.x < N) {
         double s = 0.0;
-        for (int w = 0; w < 256 / 64; ++w) s += red[threadIdx.x][w];
+        for (int w = 0; w < NT / 64; ++w) s += red[threadIdx.x][w];
         out[threadIdx.x] = s;
     }
 }
@@ -434,7 +448,7 @@ __global__ __launch_bounds__(256) void k_conservation_partial(const S* __restric
         acc[2] += C * sy;
         acc[3] += Store<S>::shifted ? 2.0 + C2 * s2 : C2 * s2;
     }
-    block_sum_store<4>(acc, partials + (size_t)blockIdx.x * 4);
+    block_sum_store<4, 256>(acc, partials + (size_t)blockIdx.x * 4);
 }
 
 // out[k] (+)= sum over nparts of partials[p * N + k]: one block of

@@ -54,7 +54,7 @@ def test_propagate_is_the_bitwise_permutation(lx, ly, xmode, ybc, layout):
     assert np.array_equal(got[ok], want[ok])
 
 
-@pytest.mark.parametrize("lx,ly", [(37, 45), (256, 130)])
+@pytest.mark.parametrize("lx,ly", [(37, 45), (256, 130), (40, 2100)])
 def test_propagate_fp32_is_bitwise(lx, ly):
     say(f"propagate fp32 {lx}x{ly}")
     t = tagged(lx, ly)
