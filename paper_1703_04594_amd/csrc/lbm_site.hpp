@@ -65,6 +65,20 @@ __device__ __forceinline__ void hop_moments(const C (&f)[NPOP], C& m0, C& sx, C&
     }
 }
 
+// The same moments of FP32 populations, accumulated in FP64.
+__device__ __forceinline__ void hop_moments_wide(const float (&f)[NPOP], double& m0, double& sx, double& sy, double& s2)
+{
+    m0 = 0.0; sx = 0.0; sy = 0.0; s2 = 0.0;
+#pragma unroll
+    for (int l = 0; l < NPOP; ++l) {
+        const double v = (double)f[l];
+        m0 += v;
+        if (EX[l] != 0) sx += (double)EX[l] * v;
+        if (EY[l] != 0) sy += (double)EY[l] * v;
+        if (R2_OF(l) != 0) s2 += (double)R2_OF(l) * v;
+    }
+}
+
 template <typename C>
 __device__ __forceinline__ C hop_dot(int l, C cux, C cuy)
 {
@@ -103,7 +117,11 @@ template <> __device__ __forceinline__ float arg_g<float>(const CollideArgs& a) 
 // equilibrium has the moments of f (mass, momentum plus tau*rho*g, energy
 // plus the work of the gravity shift), so the projection is zero; in FP32 the
 // rounded weights and scale break those identities by ~1e-8 per step, which
-// would otherwise drift mass and energy systematically.  The correction is
+// would otherwise drift mass and energy systematically.  The moment sums on
+// both sides of the projection are accumulated in FP64: an FP32 sum of 37
+// terms is off by ~1e-8, and at a site whose state changes slowly that error
+// repeats with the same sign step after step, so it would bias the conserved
+// moments just as the rounded weights do.  The correction is
 // w_l (a + b ex + c ey + d |e|^2); its Gram matrix sum_l w_l v v^T with
 // v = (1, ex, ey, |e|^2) is fixed by the quadrature (sum w = 1,
 // sum w ex^2 = 1/c^2, sum w |e|^2 = 2/c^2, sum w |e|^4 = 8/c^4), which gives
@@ -115,7 +133,13 @@ __device__ __forceinline__ void collide_site(C (&f)[NPOP], const CollideArgs& ar
     using K = ShellK<C>;
     const C omega = arg_omega<C>(args);
     C m0, sx, sy, s2;
-    hop_moments<C>(f, m0, sx, sy, s2);
+    double m0d = 0.0, sxd = 0.0, syd = 0.0, s2d = 0.0;   // FP64 sums (shifted form)
+    if constexpr (SHIFTED) {
+        hop_moments_wide(f, m0d, sxd, syd, s2d);
+        m0 = (C)m0d; sx = (C)sxd; sy = (C)syd; s2 = (C)s2d;
+    } else {
+        hop_moments<C>(f, m0, sx, sy, s2);
+    }
     const C rho = SHIFTED ? C(1) + m0 : m0;
     const C inv = C(1) / rho;
     const C ux = cscale<C>() * sx * inv;
@@ -167,13 +191,13 @@ __device__ __forceinline__ void collide_site(C (&f)[NPOP], const CollideArgs& ar
     }
     if constexpr (SHIFTED) {
         const C g = arg_g<C>(args);
-        C M0, MX, MY, M2;
-        hop_moments<C>(f, M0, MX, MY, M2);
+        double M0, MX, MY, M2;
+        hop_moments_wide(f, M0, MX, MY, M2);
         const C c2 = c2scale<C>();
-        const C d0 = m0 - M0;
-        const C dx = sx - MX;
-        const C dy = sy + rho * g / cscale<C>() - MY;
-        const C d2 = s2 + rho * (C(2) * g * uy0 + g * g) / c2 - M2;
+        const C d0 = (C)(m0d - M0);
+        const C dx = (C)(sxd - MX);
+        const C dy = (C)(syd + (1.0 + m0d) * (args.g / cscale<double>()) - MY);
+        const C d2 = (C)(s2d + (double)(rho * (C(2) * g * uy0 + g * g) / c2) - M2);
         const C ka = C(2) * d0 - C(0.5) * c2 * d2;
         const C kb = c2 * dx, kc = c2 * dy;
         const C kd = C(-0.5) * c2 * d0 + C(0.25) * c2 * c2 * d2;

@@ -227,6 +227,31 @@ def test_fp32_shifted_against_fp64_oracle(step, layout):
     assert e_rho <= 1e-5 and e_T <= 1e-5 and e_u <= 1e-5
 
 
+def test_fp32_long_run_error_does_not_drift():
+    """1000 steps of the 256x128 RT run in FP32 against the FP64 oracle.
+    Deviations of size ~0.3 w stored in FP32 round at 2^-24 ~ 6e-8 of their
+    size.  The non-conserved moments relax at rate 1/tau, so their error
+    stays at that level; the conserved moments only take the storage
+    rounding of each step, unbiased, so at worst sqrt(1000) * 6e-8 ~ 2e-6.
+    Summing the 37 moment terms in FP32 instead would add a bias of ~2e-8
+    per step with a persistent sign (~2e-5 after 1000 steps), which this
+    bound rejects."""
+    lx, ly, n = 256, 128, 1000
+    say(f"fp32 long run {lx}x{ly} {n} steps")
+    P = inputs.rt_perturbation(lx, ly, 1)
+    lat = Lattice(lx, ly, TAU, G, TB, TT, precision="fp32", step="fused", device=DEV)
+    lat.init_rt(tg(P))
+    lat.step(n)
+    ref, _ = oracle_rt(lx, ly, 1, n, openmp=True)
+    rho, ux, uy, T = (t.cpu().numpy() for t in lat.macros())
+    r_rho, r_ux, r_uy, r_T = ref.macros()
+    e_rho = np.max(np.abs(rho - r_rho) / r_rho)
+    e_T = np.max(np.abs(T - r_T) / r_T)
+    e_u = max(np.max(np.abs(ux - r_ux)), np.max(np.abs(uy - r_uy)))
+    say(f"fp32 {n}-step errors rho {e_rho:.2e} T {e_T:.2e} u {e_u:.2e}")
+    assert e_rho <= 2e-6 and e_T <= 2e-6 and e_u <= 2e-6
+
+
 def test_fp32_init_and_macros_are_fp64_exact_at_rest():
     # rest state at unit temperature: deviations are exactly zero
     lat = Lattice(16, 16, TAU, precision="fp32", ybc="periodic", device=DEV)
