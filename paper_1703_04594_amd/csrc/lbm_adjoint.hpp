@@ -32,7 +32,7 @@ struct AdjSite {
     double rho, inv, ux, uy, uys, E, th, u2, cux, cuy;
 };
 
-__device__ __forceinline__ AdjSite adj_site_scalars(double m0, double sx, double sy, double s2, const AdjArgs& a)
+__host__ __device__ __forceinline__ AdjSite adj_site_scalars(double m0, double sx, double sy, double s2, const AdjArgs& a)
 {
     AdjSite q;
     q.rho = m0;
@@ -49,13 +49,35 @@ __device__ __forceinline__ AdjSite adj_site_scalars(double m0, double sx, double
     return q;
 }
 
+// OPP.v[l]: index of the hop opposite to l (e_l' = -e_l; same shell),
+// tabulated at compile time so that indexing with an unrolled l folds.
+struct OppTable { int v[NPOP]; };
+constexpr OppTable make_opp()
+{
+    OppTable t{};
+    for (int l = 0; l < NPOP; ++l)
+        for (int k = 0; k < NPOP; ++k)
+            if (EX[k] == -EX[l] && EY[k] == -EY[l]) t.v[l] = k;
+    return t;
+}
+constexpr OppTable OPP = make_opp();
+static_assert(OPP.v[0] == 0 && OPP.v[1] == 3 && OPP.v[2] == 4 && OPP.v[36] == 32, "opposite hops");
+
 // mu <- collide^T lambda at one site, in place, given the gathered moments
 // (m0, sx, sy, s2) and Lg = sum_l lambda_l g_l; returns the site's d/dtau term.
-// The shell coefficients of the equilibrium and their derivatives are formed
-// shell by shell (populations are ordered by shell), so only one shell's worth
-// is live at a time.
-__device__ __forceinline__ double adjoint_site(double m0, double sx, double sy, double s2, double Lg,
-                                               double (&lam)[NPOP], const AdjArgs& a)
+//
+// The equilibrium factor of population l is a polynomial in a_l = xi_l . u*,
+//   P(a) = 1 + A0m1 + A1 a + A2 a^2 + a^3/6 + a^4/24,
+// with shell coefficients A0m1, A1, A2 (functions of |u*|^2 and theta).
+// collide^T needs, per shell, sum lambda P, sum e lambda dP/da, and
+// sum lambda dP/d|u|^2, sum lambda dP/dtheta.  Opposite hops l, l' share the
+// shell and have a_l' = -a_l, so each polynomial splits into an even part
+// (shared) and an odd part (sign flipped): a pair contributes through
+// lambda_l + lambda_l' and lambda_l - lambda_l' only, and every polynomial is
+// evaluated once per pair.  Shell coefficients are formed shell by shell
+// (populations are ordered by shell), so only one shell's worth is live.
+__host__ __device__ __forceinline__ double adjoint_site(double m0, double sx, double sy, double s2, double Lg,
+                                                        double (&lam)[NPOP], const AdjArgs& a)
 {
     using K = ShellK<double>;
     const AdjSite q = adj_site_scalars(m0, sx, sy, s2, a);
@@ -77,18 +99,22 @@ __device__ __forceinline__ double adjoint_site(double m0, double sx, double sy, 
                 sth += lam[0] * dA0dth;
                 continue;
             }
+            const int m = OPP.v[l];
+            if (m < l) continue;                 // each pair once, from its first hop
             const double av = hop_dot<double>(l, q.cux, q.cuy);
-            double t = av * (1.0 / 24.0) + 1.0 / 6.0;
-            t = t * av + A2;
-            t = t * av + A1;
-            const double P = 1.0 + (t * av + A0m1);
-            const double dPda = A1 + av * (2.0 * A2 + av * (0.5 + av * (1.0 / 6.0)));
-            const double Z = lam[l] * dPda;
-            sP += lam[l] * P;
+            const double a2 = av * av;
+            const double sg = lam[l] + lam[m], dl = lam[l] - lam[m];
+            // even and odd parts of P, dP/da, dP/d|u|^2, dP/dtheta
+            const double PE = (1.0 + A0m1) + a2 * (A2 + a2 * (1.0 / 24.0));
+            const double PO = av * (A1 + a2 * (1.0 / 6.0));
+            const double DE = A1 + 0.5 * a2;
+            const double DO = av * (2.0 * A2 + a2 * (1.0 / 6.0));
+            sP += sg * PE + dl * PO;
+            const double Z = dl * DE + sg * DO;   // sum over the pair of sign(e) lambda dP/da
             if (EX[l] != 0) sax += (double)EX[l] * Z;
             if (EY[l] != 0) say += (double)EY[l] * Z;
-            su2 += lam[l] * (dA0du2 + av * (-0.5 - 0.25 * av));
-            sth += lam[l] * (dA0dth + av * (K::k4(s) + av * K::k5(s)));
+            su2 += sg * (dA0du2 - 0.25 * a2) - 0.5 * (dl * av);
+            sth += sg * (dA0dth + K::k5(s) * a2) + K::k4(s) * (dl * av);
         }
         const double ws = W_SHELL[s];
         SP += ws * sP;
@@ -110,13 +136,20 @@ __device__ __forceinline__ double adjoint_site(double m0, double sx, double sy, 
     const double bjx = buxt * q.inv, bjy = buyt * q.inv;
     const double brho = bP - (buxt * q.ux + buyt * q.uy) * q.inv - 0.5 * bth * q.E * q.inv * q.inv;
     const double cjx = C * bjx, cjy = C * bjy, c2E = C2 * bE;
+    // mu_l = (1 - 1/tau) lambda_l + brho + xi_l . bj + |xi_l|^2 bE: the |e|^2
+    // part is shared by a pair, the e part flips sign
+    lam[0] = (1.0 - om) * lam[0] + brho;
 #pragma unroll
-    for (int l = 0; l < NPOP; ++l) {
-        double mu = (1.0 - om) * lam[l] + brho;
-        if (EX[l] != 0) mu += (double)EX[l] * cjx;
-        if (EY[l] != 0) mu += (double)EY[l] * cjy;
-        if (R2_OF(l) != 0) mu += (double)R2_OF(l) * c2E;
-        lam[l] = mu;
+    for (int l = 1; l < NPOP; ++l) {
+        const int m = OPP.v[l];
+        if (m < l) continue;
+        const double even = brho + (double)R2_OF(l) * c2E;
+        double odd = 0.0;
+        if (EX[l] != 0) odd += (double)EX[l] * cjx;
+        if (EY[l] != 0) odd += (double)EY[l] * cjy;
+        const double ll = lam[l], lm = lam[m];
+        lam[l] = (1.0 - om) * ll + (even + odd);
+        lam[m] = (1.0 - om) * lm + (even - odd);
     }
     return dtau;
 }
@@ -127,6 +160,13 @@ __device__ __forceinline__ void block_sum1(double v, double* __restrict__ partia
     double a[1] = {v};
     block_sum_store<1, SITE_THREADS>(a, partials + (size_t)blockIdx.y * gridDim.x + blockIdx.x);
 }
+
+// k_adj_collide_push is launched with ADJ_LDS_RESERVE bytes of dynamic LDS
+// that it never touches: with 160 KB of LDS per CU this admits two 256-thread
+// workgroups per CU, i.e. two waves per SIMD.  Its ~166 VGPRs would allow
+// three, but three measured slower (2.8% with FP64 lambda, 0.7% with FP32):
+// the extra waves mostly add concurrent DRAM streams to an HBM-bound pass.
+constexpr unsigned ADJ_LDS_RESERVE = 56 * 1024;
 
 template <typename S, typename L, bool WALLS>
 __global__ __launch_bounds__(SITE_THREADS) void k_adj_collide_push(

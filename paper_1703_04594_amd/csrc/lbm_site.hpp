@@ -80,7 +80,7 @@ __device__ __forceinline__ void hop_moments_wide(const float (&f)[NPOP], double&
 }
 
 template <typename C>
-__device__ __forceinline__ C hop_dot(int l, C cux, C cuy)
+__host__ __device__ __forceinline__ C hop_dot(int l, C cux, C cuy)
 {
     C a = C(0);
     if (EX[l] != 0 && EY[l] != 0) a = C(EX[l]) * cux + C(EY[l]) * cuy;
