@@ -44,10 +44,12 @@ def kernel_source_sha256():
     return h.hexdigest()
 
 
-def measured_traffic(kernel_prefix):
-    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
-    runs, or None if the kernels changed since they were taken."""
-    path = os.path.join(ROOT, "profiles", "d2q37_2048x4096_hbm_traffic.json")
+def measured_counters(kernel_prefix):
+    """Per-launch rocprofv3 counter figures of a kernel on the 2048x4096
+    lattice -- HBM bytes (FETCH_SIZE/WRITE_SIZE, calibrated) and VALU FLOPs
+    (SQ_INSTS_VALU_FLOPS_FP64/FP32) -- from the committed profile, or None
+    if the kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "d2q37_2048x4096_counters.json")
     try:
         with open(path) as fh:
             rec = json.load(fh)
@@ -57,8 +59,22 @@ def measured_traffic(kernel_prefix):
         return None
     for name, v in rec["kernels"].items():
         if name.startswith(kernel_prefix):
-            return v["traffic_bytes"]
+            return v
     return None
+
+
+def measured_traffic(kernel_prefix):
+    v = measured_counters(kernel_prefix)
+    return None if v is None else v["traffic_bytes"]
+
+
+def flop_fraction(kernel_prefix, seconds):
+    """Achieved FP64 and FP32 FLOP rate of one launch over the vector peaks."""
+    v = measured_counters(kernel_prefix)
+    if v is None or "flops_fp64" not in v:
+        return None
+    return {"fp64": round(v["flops_fp64"] / seconds / 1e12 / FP64_PEAK_TFLOPS, 4),
+            "fp32": round(v["flops_fp32"] / seconds / 1e12 / FP32_PEAK_TFLOPS, 4)}
 
 
 def log(msg):
@@ -76,6 +92,37 @@ def time_launches(fn, stream, reps):
     end.record(stream)
     end.synchronize()
     return start.elapsed_time(end) / reps * 1e-3
+
+
+def copy_reference(nbytes, stream, reps=20):
+    """Plain device copy of nbytes (csrc/copy_probe.hip) with 1, 2 and 4 KB per
+    workgroup, timed like the lattice kernels; returns GB/s moved (read +
+    write) per workgroup size."""
+    import ctypes
+
+    import torch
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_1703_04594_amd", "libcopyprobe.so"))
+    lib.cp_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_void_p]
+    lib.cp_copy.restype = ctypes.c_int
+    a = torch.arange(nbytes // 8, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    out = {}
+    for bb in (1024, 2048, 4096):
+        def go():
+            rc = lib.cp_copy(a.data_ptr(), b.data_ptr(), a.numel() * 8, bb, stream.cuda_stream)
+            if rc:
+                raise RuntimeError(f"cp_copy failed ({rc})")
+        go()
+        b.zero_()
+        go()
+        stream.synchronize()
+        if not torch.equal(a, b):
+            raise RuntimeError("reference copy produced wrong data")
+        t = time_launches(go, stream, reps)
+        out[f"{bb // 1024}KB_per_workgroup"] = round(2 * a.numel() * 8 / t / 1e9, 1)
+    del a, b
+    torch.cuda.empty_cache()
+    return out
 
 
 def run(args):
@@ -131,6 +178,9 @@ def run(args):
     del lat
     torch.cuda.empty_cache()
 
+    log("bench: reference copy of one lattice's populations")
+    copy_ref = copy_reference(37 * 8 * sites, s)
+
     log("bench: FP32-shifted")
     lat = make("fp32", "fused")
     fp32_mlups, _ = mlups(lat, args.steps, args.warmup)
@@ -180,10 +230,18 @@ def run(args):
                       "propagate_fp64": round(t_prop * 1e3, 4), "collide_fp64": round(t_coll * 1e3, 4),
                       "adjoint_step_fp32": round(t_adj["fp64"] * 1e3, 4),
                       "adjoint_step_fp32_lambda32": round(t_adj["fp32"] * 1e3, 4), "step_fp32": round(t_fwd32 * 1e3, 4)},
+        "copy_reference_GBps": copy_ref,
+        "propagate_fp64_over_copy": round(bytes_fp64 / t_prop / 1e9 / max(copy_ref.values()), 3),
         "hbm_frac": {"fused_fp64": round(bytes_fp64 / t_fused / 1e9 / HBM_PEAK_GBS, 3),
                      "fused_fp32": round(bytes_fp32 / t_fused32 / 1e9 / HBM_PEAK_GBS, 3),
                      "propagate_fp64": round(bytes_fp64 / t_prop / 1e9 / HBM_PEAK_GBS, 3),
                      "collide_fp64": round(bytes_fp64 / t_coll / 1e9 / HBM_PEAK_GBS, 3)},
+        "flop_frac": None if (lx, ly) != (2048, 4096) else {
+            "fused_fp64": flop_fraction("lbm::k_step_fused<double, true, true>", t_fused),
+            "collide_fp64": flop_fraction("lbm::k_collide<double, true>", t_coll),
+            "fused_fp32": flop_fraction("lbm::k_step_fused<float, true, true>", t_fused32),
+            "adjoint_fp64_lambda": flop_fraction("lbm::k_adj_collide_push<float, double, true>", t_adj["fp64"]),
+            "adjoint_fp32_lambda": flop_fraction("lbm::k_adj_collide_push<float, float, true>", t_adj["fp32"])},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic("lbm::k_step_fused<double, true, true>") if (lx, ly) == (2048, 4096) else None,
@@ -327,7 +385,8 @@ def cpu_baseline(args, budget_s=15.0):
 
 def profile_workload(args):
     """Short fixed sequence for rocprofv3 runs: a plain device copy of known
-    size (calibrates the HBM byte counters), then FP64 and FP32 fused steps,
+    size (calibrates the HBM byte counters), the reference copy of one
+    lattice's populations, then FP64 and FP32 fused steps,
     FP64 and FP32 split steps, and adjoint steps over FP32 states with FP64
     and FP32 lambda, all on the bench lattice."""
     import torch
@@ -343,6 +402,7 @@ def profile_workload(args):
         b.copy_(a)                     # 1 GiB read + 1 GiB written per dispatch
     torch.cuda.synchronize()
     del a, b
+    copy_reference(37 * 8 * lx * ly, torch.cuda.current_stream(), reps=5)
     P = torch.tensor(inputs.rt_perturbation(lx, ly, 1), device=dev)
     for prec in ("fp64", "fp32"):
         lat = Lattice(lx, ly, 0.7, -1e-5, 4 / 3, 2 / 3, precision=prec, step="fused", device=dev)

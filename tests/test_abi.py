@@ -65,3 +65,18 @@ def test_python_binding_refuses_missing_library(monkeypatch):
     monkeypatch.setattr(lbm, "LIB_PATH", "/nonexistent/liblbm.so")
     with pytest.raises(lbm.LBMError):
         lbm.lib()
+
+
+def test_reference_copy_library_rejects_bad_arguments():
+    """The benchmark's calibration copy (csrc/copy_probe.hip) loads, exports
+    cp_copy, and refuses invalid arguments before any HIP call."""
+    path = os.path.join(os.path.dirname(lbm.LIB_PATH), "libcopyprobe.so")
+    lib = ctypes.CDLL(path)
+    f = lib.cp_copy
+    f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_void_p]
+    f.restype = ctypes.c_int
+    assert f(None, None, 16, 2048, None) == 1                  # null pointers
+    assert f(0x1000, 0x100000, 24, 2048, None) == 1            # size not a multiple of 16
+    assert f(0x1008, 0x100000, 32, 2048, None) == 1            # misaligned source
+    assert f(0x1000, 0x1010, 64, 2048, None) == 1              # overlapping ranges
+    assert f(0x1000, 0x100000, 64, 3000, None) == 1            # unsupported workgroup size
