@@ -383,6 +383,27 @@ def cpu_baseline(args, budget_s=15.0):
             "kind": "oracle", "sample": f"{n} FP64 steps of the {lx}x{ly} RT lattice after 1 untimed step"}
 
 
+def cpu_oracle_serial(lx=256, ly=128, n=50):
+    """The serial oracle (one core) on the small 256x128 RT lattice, 50 steps
+    after one untimed step."""
+    import numpy as np
+
+    import oracle
+    from paper_1703_04594_amd import inputs
+
+    P = inputs.rt_perturbation(lx, ly, 1)
+    y = np.arange(ly)[None, :]
+    T0 = 1.0 - np.tanh((y - (ly - 1) / 2 - P) / 2.0) / 3.0
+    L = oracle.RefLattice(lx, ly, 0.7, -1e-5, 4 / 3, 2 / 3, openmp=False)
+    L.init((8 / 9) / T0, 0.0, 0.0, T0)
+    L.step(1)
+    t0 = time.perf_counter()
+    L.step(n)
+    dt = time.perf_counter() - t0
+    return {"value": round(lx * ly * n / dt / 1e6, 3), "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "seconds": round(dt, 3), "sample": f"{n} FP64 steps of the {lx}x{ly} RT lattice, serial build"}
+
+
 def profile_workload(args):
     """Short fixed sequence for rocprofv3 runs: a plain device copy of known
     size (calibrates the HBM byte counters), the reference copy of one
@@ -444,7 +465,7 @@ def main():
                     help="run the short fixed kernel sequence used under rocprofv3")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on one GPU only; multi-GPU X-slab sharding is not implemented",
+        print("bench.py: runs on one GPU only; multi-GPU X-slab sharding is not implemented",
               file=sys.stderr)
         sys.exit(2)
     if args.profile:
@@ -456,6 +477,7 @@ def main():
         res["adjoint_1024x2048_10000_steps"] = adjoint_at_scale()
         res["adjoint_1024x2048_10000_steps_lambda32"] = adjoint_at_scale(lam="fp32")
     res["cpu_baseline"] = None if args.skip_cpu else cpu_baseline(args)
+    res["cpu_oracle_serial_256x128"] = None if args.skip_cpu else cpu_oracle_serial()
     print(json.dumps(res), flush=True)
 
 
