@@ -5,8 +5,8 @@
 // propagate's bandwidth can be quoted as a fraction of a plain copy measured
 // on the same GPU in the same run.  dst[i] = src[i] over `bytes` bytes in
 // 16-byte vectors, one workgroup per chunk of `block_bytes` bytes (1024, 2048
-// or 4096: 64, 128 or 256 threads), non-temporal stores, hardware block
-// order -- the same per-workgroup shape as propagate.
+// or 4096: 64, 128 or 256 threads), non-temporal loads and stores, hardware
+// block order (the fastest plain copy measured on MI355X used this form).
 //
 // int cp_copy(const void* src, void* dst, size_t bytes, int block_bytes,
 //             void* hip_stream)
@@ -27,7 +27,7 @@ template <int T>
 __global__ __launch_bounds__(T) void k_copy(const v2* __restrict__ src, v2* __restrict__ dst, size_t n)
 {
     const size_t i = (size_t)blockIdx.x * T + threadIdx.x;
-    if (i < n) __builtin_nontemporal_store(src[i], dst + i);
+    if (i < n) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
 }
 
 template <int T>

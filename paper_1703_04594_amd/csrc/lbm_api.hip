@@ -172,18 +172,22 @@ lbm_status launch_propagate(lbm_ctx* c, const S* src, S* dst)
     constexpr int VEC = sizeof(S) == 8 ? 2 : 4;
     constexpr int UNROLL = PROP_UNROLL;
     constexpr int CH = PROP_THREADS * VEC * UNROLL;
-    const unsigned nch = (unsigned)((g.ly + CH - 1) / CH);
+    const size_t nch = (size_t)((g.ly + CH - 1) / CH);
+    const size_t nblk = nch * NPOP * (size_t)g.lx;
+    if (nblk > 0xffffffffull) return fail(c, LBM_ERR_SIZE, "propagate: lattice too large for one grid");
+    const unsigned gx = nblk < PROP_GRID_X ? (unsigned)nblk : PROP_GRID_X;
+    const dim3 grid(gx, (unsigned)((nblk + gx - 1) / gx));
     const bool cols = c->p.layout == LBM_LAYOUT_COLUMNS;
-    const dim3 grid = cols ? dim3(nch, NPOP, g.lx) : dim3(nch, g.lx, NPOP);
     const bool wrap = c->p.xmode == LBM_X_WRAP;
+    const unsigned nb = (unsigned)nblk;
     if (wrap && cols)
-        hipLaunchKernelGGL((k_propagate<S, VEC, UNROLL, true, true>), grid, dim3(PROP_THREADS), 0, c->stream, src, dst, g);
+        hipLaunchKernelGGL((k_propagate<S, VEC, UNROLL, true, true>), grid, dim3(PROP_THREADS), 0, c->stream, src, dst, g, nb);
     else if (wrap)
-        hipLaunchKernelGGL((k_propagate<S, VEC, UNROLL, true, false>), grid, dim3(PROP_THREADS), 0, c->stream, src, dst, g);
+        hipLaunchKernelGGL((k_propagate<S, VEC, UNROLL, true, false>), grid, dim3(PROP_THREADS), 0, c->stream, src, dst, g, nb);
     else if (cols)
-        hipLaunchKernelGGL((k_propagate<S, VEC, UNROLL, false, true>), grid, dim3(PROP_THREADS), 0, c->stream, src, dst, g);
+        hipLaunchKernelGGL((k_propagate<S, VEC, UNROLL, false, true>), grid, dim3(PROP_THREADS), 0, c->stream, src, dst, g, nb);
     else
-        hipLaunchKernelGGL((k_propagate<S, VEC, UNROLL, false, false>), grid, dim3(PROP_THREADS), 0, c->stream, src, dst, g);
+        hipLaunchKernelGGL((k_propagate<S, VEC, UNROLL, false, false>), grid, dim3(PROP_THREADS), 0, c->stream, src, dst, g, nb);
     return check_launch(c, "propagate");
 }
 

@@ -136,34 +136,44 @@ template <> struct VecA<double, 2> { typedef double T __attribute__((ext_vector_
 template <> struct VecA<float, 2> { typedef float T __attribute__((ext_vector_type(2))); };
 template <> struct VecA<float, 4> { typedef float T __attribute__((ext_vector_type(4))); };
 
-// propagate: 128 threads, one 16-byte vector each, so a block moves 2 KB of one
-// segment.  Measured on the 2048x4096 lattice: 2 KB blocks beat 1, 4, 8 and
-// 16 KB ones, and the hardware block order (all XCDs sweeping the same region
-// of memory together) beats an XCD-contiguous renumbering.
-constexpr int PROP_THREADS = 128;
+// propagate: 256 threads, one 16-byte vector each, so a workgroup moves 4 KB
+// of one segment.  Loads and stores are both non-temporal (each byte is read
+// once and written once).  Workgroups are numbered linearly, chunk fastest,
+// then the population index (COLS layout: the 37 segments of a column are
+// contiguous) or the column (planes layout), so consecutive workgroups stream
+// consecutive memory, and they run in hardware order (all XCDs sweep the same
+// region of memory together).  Measured on the 2048x4096 lattice, this beat
+// 1, 2, 8 and 16 KB workgroups, temporal loads, an XCD-contiguous
+// renumbering and a 3-D (chunk, population, column) grid.
+constexpr int PROP_THREADS = 256;
 constexpr int PROP_UNROLL = 1;
+// widest x dimension of the propagate grid (workgroups); larger launches add
+// rows, still dispatched in linear order
+constexpr unsigned PROP_GRID_X = 1u << 20;
 
-// Blocks are numbered so that consecutive blocks stream consecutive memory:
-// chunk fastest, then the population index (COLS layout: the 37 segments of a
-// column are contiguous) or the column (planes layout).
 template <typename S, int VEC, int UNROLL, bool WRAP, bool COLS>
-__global__ __launch_bounds__(PROP_THREADS) void k_propagate(const S* __restrict__ src, S* __restrict__ dst, Geo g)
+__global__ __launch_bounds__(PROP_THREADS) void k_propagate(const S* __restrict__ src, S* __restrict__ dst, Geo g,
+                                                            unsigned nblk)
 {
     using VU = typename VecT<S, VEC>::T;
     using VA = typename VecA<S, VEC>::T;
-    const int l = COLS ? blockIdx.y : blockIdx.z;
-    const int x = COLS ? blockIdx.z : blockIdx.y;
+    const unsigned L = blockIdx.y * gridDim.x + blockIdx.x;
+    if (L >= nblk) return;
+    const int nch = (g.ly + PROP_THREADS * VEC * UNROLL - 1) / (PROP_THREADS * VEC * UNROLL);
+    const int ch = (int)(L % (unsigned)nch), rest = (int)(L / (unsigned)nch);
+    const int l = COLS ? rest % NPOP : rest / g.lx;
+    const int x = COLS ? rest / NPOP : rest % g.lx;
     const int ex = c_hops.ex[l], ey = c_hops.ey[l];
     int xs = x - ex;
     if (WRAP) xs = wrap_x(xs, g.lx);
     const S* sp = src + (size_t)l * g.ps + g.origin + (long long)xs * g.cs - ey;
     S* dp = dst + (size_t)l * g.ps + g.origin + (long long)x * g.cs;
-    const int y0 = blockIdx.x * (PROP_THREADS * VEC * UNROLL) + threadIdx.x * VEC;
+    const int y0 = ch * (PROP_THREADS * VEC * UNROLL) + threadIdx.x * VEC;
     VU v[UNROLL];
 #pragma unroll
     for (int u = 0; u < UNROLL; ++u) {
         const int y = y0 + u * PROP_THREADS * VEC;
-        if (y < g.ly) v[u] = *reinterpret_cast<const VU*>(sp + y);
+        if (y < g.ly) v[u] = __builtin_nontemporal_load(reinterpret_cast<const VU*>(sp + y));
     }
 #pragma unroll
     for (int u = 0; u < UNROLL; ++u) {

@@ -54,6 +54,27 @@ def test_propagate_is_the_bitwise_permutation(lx, ly, xmode, ybc, layout):
     assert np.array_equal(got[ok], want[ok])
 
 
+def test_propagate_multi_row_grid_is_bitwise():
+    """2048x8192 FP64: 1,212,416 propagate workgroups, more than one grid row
+    of 2^20, so the launch takes its 2-D form with a partial last row."""
+    lx, ly = 2048, 8192
+    say(f"propagate permutation {lx}x{ly} (multi-row grid)")
+    t = tagged(lx, ly)
+    lat = Lattice(lx, ly, TAU, device=DEV)
+    lat.set_pops(tg(t))
+    lat.propagate()
+    got = lat.get_pops().cpu().numpy()
+    del lat
+    torch.cuda.empty_cache()
+    ref = oracle.RefLattice(lx, ly, TAU)
+    ref.set_pops(t)
+    del t
+    ref.propagate()
+    want = ref.get_pops()
+    ok = ~np.isnan(want)
+    assert np.array_equal(got[ok], want[ok])
+
+
 @pytest.mark.parametrize("lx,ly", [(37, 45), (256, 130), (40, 2100)])
 def test_propagate_fp32_is_bitwise(lx, ly):
     say(f"propagate fp32 {lx}x{ly}")
