@@ -11,14 +11,20 @@
 //    T = (E / rho - |u|^2) / 2 and the gravity shift.
 //  d step / d tau:  -(1/tau^2) <lambda, f^eq - g> + <lambda / tau, d f^eq / d tau>
 //    (the last term through u* = u + tau g, T* = T + tau (1 - tau) g^2 / 2).
-//  propagate^T: the pull g_l(s) = f_l(s - e_l) transposes to a push:
-//    lambda_n,l(s - e_l) = mu_l(s).  Pushes whose target lies outside the
-//    lattice in y belong to wall slots; they land in the ghost rows of the
-//    lambda buffer.
-//  bc^T: a wall slot (l, s) carries E^w_l rho(m) with rho(m) = sum_k f_k(m) at
-//    the mirror site m, so every population of m receives E^w_l mu_l(s); the
-//    ghost row value at m's column is exactly that mu_l(s).  Interior slots
-//    that no site pushes to (their hop leaves through the wall) get 0.
+//  propagate^T and bc^T, evaluated as a pull by the step that needs lambda_n
+//  (the next reverse step, or the readers of lambda): the buffer holds mu at
+//  each site, and
+//    lambda_n,l(s) = [s + e_l inside the lattice] mu_l(s + e_l) + beta(s),
+//  since the pull g_l(s') = f_l(s' - e_l) reads f_l(s) only from s' = s + e_l,
+//  and a slot s' whose source s is inside is never a wall slot.  beta (rows
+//  0-2 and ly-3..ly-1 only) is bc^T: a wall slot (l, w) carries
+//  E^w_l rho(m) with rho(m) = sum_k f_k(m) at the mirror site m of its
+//  source, so every population of m receives E^w_l mu_l(w).  For a site s
+//  in row r from a wall, the wall slots mirroring onto it are
+//  w = (x + e_x,l, e_n - 1 - r) counted from that wall, for each l whose
+//  component e_n into the lattice exceeds r.
+//  Storing mu at its own site keeps every store aligned (a push would write
+//  e_y-shifted partial lines) and folds bc^T into the gather.
 #pragma once
 
 #include "lbm_kernels.hpp"
@@ -161,16 +167,63 @@ __device__ __forceinline__ void block_sum1(double v, double* __restrict__ partia
     block_sum_store<1, SITE_THREADS>(a, partials + (size_t)blockIdx.y * gridDim.x + blockIdx.x);
 }
 
-// k_adj_collide_push is launched with ADJ_LDS_RESERVE bytes of dynamic LDS
-// that it never touches: with 160 KB of LDS per CU this admits two 256-thread
-// workgroups per CU, i.e. two waves per SIMD.  Its ~166 VGPRs would allow
-// three, but three measured slower (2.8% with FP64 lambda, 0.7% with FP32):
-// the extra waves mostly add concurrent DRAM streams to an HBM-bound pass.
-constexpr unsigned ADJ_LDS_RESERVE = 56 * 1024;
+// lambda_{n+1} at site (x, y) (see the header): from a buffer that holds mu
+// of the later step (GATHER), or lambda itself at each site (after a seed or
+// an explicit set).  Loads are unconditional: in the three rows next to a
+// wall the e_y-shifted ones reach into the ghost rows, and those values are
+// replaced by 0 below.
+template <typename L, bool WALLS, bool GATHER>
+__device__ __forceinline__ void load_lambda(const L* __restrict__ buf, const Geo& lg, const WallTable& wt,
+                                            int x, int y, double (&lam)[NPOP])
+{
+    const unsigned yd = (unsigned)y * (unsigned)sizeof(L);
+    if (!GATHER) {
+        const L* col = buf + lg.origin + (long long)x * lg.cs;
+#pragma unroll
+        for (int l = 0; l < NPOP; ++l) lam[l] = (double)ld_at(col + (size_t)l * lg.ps, yd);
+        return;
+    }
+    if (!WALLS) {
+#pragma unroll
+        for (int l = 0; l < NPOP; ++l) {
+            const int xs = wrap_x(x + EX[l], lg.lx);
+            int ys = y + EY[l];
+            ys = ys < 0 ? ys + lg.ly : (ys >= lg.ly ? ys - lg.ly : ys);
+            lam[l] = (double)buf[(size_t)l * lg.ps + lg.origin + (long long)xs * lg.cs + ys];
+        }
+        return;
+    }
+#pragma unroll
+    for (int l = 0; l < NPOP; ++l) {
+        const int xs = wrap_x(x + EX[l], lg.lx);
+        lam[l] = (double)ld_at(buf + (size_t)l * lg.ps + lg.origin + (long long)xs * lg.cs + EY[l], yd);
+    }
+    if (y < 3 || y >= lg.ly - 3) {
+        const int wall = y < 3 ? 0 : 1;
+        const int r = wall == 0 ? y : lg.ly - 1 - y;       // row counted from the wall
+        double beta = 0.0;
+#pragma unroll
+        for (int l = 0; l < NPOP; ++l) {
+            if (EY[l] == 0) continue;
+            const int en = wall == 0 ? EY[l] : -EY[l];      // hop component into the lattice
+            if (-en > r) lam[l] = 0.0;                      // s + e_l lies beyond the wall
+            if (en > r) {                                   // a wall slot that mirrors onto s
+                const int yw = wall == 0 ? en - 1 - r : lg.ly - en + r;
+                const int xw = wrap_x(x + EX[l], lg.lx);
+                beta += wt.ew[wall][l] * (double)buf[(size_t)l * lg.ps + lg.origin + (long long)xw * lg.cs + yw];
+            }
+        }
+#pragma unroll
+        for (int l = 0; l < NPOP; ++l) lam[l] += beta;
+    }
+}
 
-template <typename S, typename L, bool WALLS>
-__global__ __launch_bounds__(SITE_THREADS) void k_adj_collide_push(
-    const S* __restrict__ fn, Geo g, const L* __restrict__ lam_in, L* __restrict__ lam_out, Geo lg,
+// One reverse step at site (x, y): lambda_{n+1} (load_lambda), the gather
+// g = bc(propagate(f_n)) of the snapshot f_n, collide^T, and mu stored at the
+// site (aligned, non-temporal); the d/dtau term goes to partials.
+template <typename S, typename L, bool WALLS, bool GATHER>
+__global__ __launch_bounds__(SITE_THREADS) void k_adj_collide(
+    const S* __restrict__ fn, Geo g, const L* __restrict__ lam_in, L* __restrict__ mu_out, Geo lg,
     AdjArgs a, const double* __restrict__ wall_rho, WallTable wt, double* __restrict__ partials)
 {
     const SiteBlock sb = site_block(g);
@@ -180,13 +233,10 @@ __global__ __launch_bounds__(SITE_THREADS) void k_adj_collide_push(
         using Cc = typename Store<S>::C;
         const unsigned yb = (unsigned)y * (unsigned)sizeof(S);
         const unsigned yd = (unsigned)y * (unsigned)sizeof(L);
-        // lambda_{n+1} at this site and the raw gather of f_n (storage
-        // precision; all loads unconditional -- wall slots read ghost rows and
-        // are replaced below)
         double lam[NPOP];
-        const L* lcol = lam_in + lg.origin + (long long)x * lg.cs;
-#pragma unroll
-        for (int l = 0; l < NPOP; ++l) lam[l] = (double)ld_at(lcol + (size_t)l * lg.ps, yd);
+        load_lambda<L, WALLS, GATHER>(lam_in, lg, wt, x, y, lam);
+        // the raw gather of f_n (storage precision; unconditional -- wall
+        // slots read ghost rows and are replaced below)
         Cc gl[NPOP];
 #pragma unroll
         for (int l = 0; l < NPOP; ++l) {
@@ -231,65 +281,11 @@ __global__ __launch_bounds__(SITE_THREADS) void k_adj_collide_push(
             }
         }
         dtau = adjoint_site(m0, sx, sy, s2, Lg, lam, a);
-        // propagate^T: push mu_l to (x - ex, y - ey); beyond a wall it lands
-        // in the ghost rows (read by k_adj_bc_fix)
+        L* mcol = mu_out + lg.origin + (long long)x * lg.cs;
 #pragma unroll
-        for (int l = 0; l < NPOP; ++l) {
-            const int xd = wrap_x(x - EX[l], g.lx);
-            if (WALLS) {
-                st_at(lam_out + (size_t)l * lg.ps + lg.origin + (long long)xd * lg.cs - EY[l], yd, (L)lam[l]);
-            } else {
-                int ys = y - EY[l];
-                ys = ys < 0 ? ys + g.ly : (ys >= g.ly ? ys - g.ly : ys);
-                lam_out[(size_t)l * lg.ps + lg.origin + (long long)xd * lg.cs + ys] = (L)lam[l];
-            }
-        }
+        for (int l = 0; l < NPOP; ++l) st_nt(mcol + (size_t)l * lg.ps, yd, (L)lam[l]);
     }
     block_sum1(dtau, partials);
-}
-
-// bc^T and the zeroing of slots nobody pushes to.  A block handles one wall
-// and BCF_COLS columns, one thread per (column, population): each thread loads
-// its 3 ghost values (wall-slot mu pushed beyond the wall) and 3 interior
-// values, the ghost contributions E^w_l mu are summed over the 37 populations
-// of a column in LDS in fixed order (beta of each of the 3 rows), and every
-// interior value becomes (pushed ? value : 0) + beta.
-constexpr int BCF_COLS = 6;
-
-template <typename L>
-__global__ __launch_bounds__(256) void k_adj_bc_fix(L* __restrict__ lam, Geo lg, const WallTable* __restrict__ wt)
-{
-    __shared__ double part[BCF_COLS][3][NPOP];
-    const int wall = blockIdx.y;
-    const int t = threadIdx.x;
-    const int cj = t / NPOP, l = t - cj * NPOP;
-    const int x = blockIdx.x * BCF_COLS + cj;
-    const bool act = t < BCF_COLS * NPOP && x < lg.lx;
-    L* seg = nullptr;
-    double in[3] = {0.0, 0.0, 0.0};
-    if (act) {
-        const int ey = c_hops.ey[l];
-        const int en = wall == 0 ? ey : -ey;
-        const double ew = wt->ew[wall][l];
-        seg = lam + (size_t)l * lg.ps + lg.origin + (long long)x * lg.cs;
-#pragma unroll
-        for (int r = 0; r < 3; ++r) {
-            const int y = wall == 0 ? r : lg.ly - 1 - r;
-            const int yg = wall == 0 ? -r - 1 : lg.ly + r;
-            part[cj][r][l] = (en >= r + 1) ? ew * (double)seg[yg] : 0.0;
-            in[r] = (-en > r) ? 0.0 : (double)seg[y];
-        }
-    }
-    __syncthreads();
-    if (act) {
-#pragma unroll
-        for (int r = 0; r < 3; ++r) {
-            double beta = 0.0;
-            for (int k = 0; k < NPOP; ++k) beta += part[cj][r][k];
-            const int y = wall == 0 ? r : lg.ly - 1 - r;
-            seg[y] = (L)(in[r] + beta);
-        }
-    }
 }
 
 // lambda_l = d(x,y) dT/df_l = d (|xi_l - u|^2 - 2T) / (2 rho), with
@@ -320,9 +316,9 @@ __global__ __launch_bounds__(SITE_THREADS) void k_adj_seed_T(const S* __restrict
 // dL/dP from lambda_0 for f_0 = f^eq(rho0(P), 0, T0(P)):
 //   T0 = t_mid - t_amp tanh(z), z = (y - y_mid - P) / width, rho0 = p0 / T0,
 //   f^eq_l(rho, 0, T) = w_l rho (1 + th K1 + th^2 K3), th = T - 1.
-template <typename L>
-__global__ __launch_bounds__(SITE_THREADS) void k_adj_init_rt(const L* __restrict__ lam, Geo lg, const double* __restrict__ P,
-                                                           RtProfile pr, double* __restrict__ dP)
+template <typename L, bool WALLS, bool GATHER>
+__global__ __launch_bounds__(SITE_THREADS) void k_adj_init_rt(const L* __restrict__ lam_buf, Geo lg, WallTable wt,
+                                                           const double* __restrict__ P, RtProfile pr, double* __restrict__ dP)
 {
     using K = ShellK<double>;
     const SiteBlock sb = site_block(lg);
@@ -335,29 +331,41 @@ __global__ __launch_bounds__(SITE_THREADS) void k_adj_init_rt(const L* __restric
     const double dT = pr.t_amp * (1.0 - th_z * th_z) / pr.width;
     const double dr = -pr.p0 / (T0 * T0) * dT;
     const double th = T0 - 1.0;
-    const L* lp = lam + lg.origin + (long long)x * lg.cs + y;
+    double lam[NPOP];
+    load_lambda<L, WALLS, GATHER>(lam_buf, lg, wt, x, y, lam);
     double acc = 0.0;
 #pragma unroll
     for (int l = 0; l < NPOP; ++l) {
         const int sh = SHELL[l];
         const double Pl = 1.0 + th * (K::k1(sh) + th * K::k3(sh));
         const double dPl = K::k1(sh) + 2.0 * th * K::k3(sh);
-        acc += (double)lp[(size_t)l * lg.ps] * W_SHELL[sh] * (Pl * dr + r0 * dPl * dT);
+        acc += lam[l] * W_SHELL[sh] * (Pl * dr + r0 * dPl * dT);
     }
     dP[s] = acc;
 }
 
-// lambda canonical FP64 [37][lx][ly] <-> padded buffer of type L
-template <typename L, bool TO_CANON>
-__global__ __launch_bounds__(256) void k_lambda_canon(L* __restrict__ buf, double* __restrict__ canon, Geo g)
+// lambda (load_lambda) -> canonical FP64 [37][lx][ly], one thread per site
+template <typename L, bool WALLS, bool GATHER>
+__global__ __launch_bounds__(SITE_THREADS) void k_lambda_to_canon(const L* __restrict__ buf, Geo lg, WallTable wt,
+                                                               double* __restrict__ canon)
+{
+    const SiteBlock sb = site_block(lg);
+    const int x = sb.x, y = sb.y;
+    if (y >= lg.ly) return;
+    double lam[NPOP];
+    load_lambda<L, WALLS, GATHER>(buf, lg, wt, x, y, lam);
+#pragma unroll
+    for (int l = 0; l < NPOP; ++l) canon[((size_t)l * lg.lx + x) * lg.ly + y] = lam[l];
+}
+
+// canonical FP64 [37][lx][ly] -> lambda at each site of a padded buffer of type L
+template <typename L>
+__global__ __launch_bounds__(256) void k_lambda_from_canon(L* __restrict__ buf, const double* __restrict__ canon, Geo g)
 {
     const int l = blockIdx.z, x = blockIdx.y;
     const int y = blockIdx.x * 256 + threadIdx.x;
     if (y >= g.ly) return;
-    const size_t pi = (size_t)l * g.ps + g.origin + (long long)x * g.cs + y;
-    const size_t ci = ((size_t)l * g.lx + x) * g.ly + y;
-    if (TO_CANON) canon[ci] = (double)buf[pi];
-    else buf[pi] = (L)canon[ci];
+    buf[(size_t)l * g.ps + g.origin + (long long)x * g.cs + y] = (L)canon[((size_t)l * g.lx + x) * g.ly + y];
 }
 
 }  // namespace lbm

@@ -29,7 +29,6 @@ struct Plan {
     size_t state_bytes; // snapshot: population buffer + its wall densities
     size_t off_buf[2];
     size_t off_wall;  // 2 x 6 * lx doubles (double-buffered wall densities)
-    size_t off_tab;   // device copy of the wall table (E^w, w)
     size_t off_part;  // RED_BLOCKS * 4 doubles, then 2 doubles of loss/dtau scratch
     size_t off_lam[2];
     size_t off_apart; // adjoint: one double per collide block
@@ -86,7 +85,6 @@ Plan plan(const lbm_params* p)
     pl.off_buf[0] = off; off += pl.buf_bytes;
     pl.off_buf[1] = off; off += pl.buf_bytes;
     pl.off_wall = off; off += 2 * pl.wall_bytes;
-    pl.off_tab = off; off += align_up(sizeof(WallTable), ALIGN);
     pl.off_part = off; off += align_up(((size_t)RED_BLOCKS * 4 + 2) * 8, ALIGN);
     if (p->adjoint) {
         const size_t lb = align_up((size_t)pl.lgeo.total * (p->adjoint == 2 ? 4 : 8), ALIGN);
@@ -112,6 +110,9 @@ struct lbm_ctx {
     bool have_prev;    // the other buffer holds the state before the last propagate
     int lam_cur;
     bool have_lambda;
+    // lambda buffer lam_cur holds mu of the last reverse step (lambda is its
+    // propagate^T + bc^T gather) rather than lambda itself
+    bool lam_is_mu;
     // wall densities (rows 0..2 and ly-3..ly-1) of population buffer wr_buf
     // (-1: none) live in wall table wr_cur; the other table receives the
     // densities the next collide or fused step writes
@@ -123,7 +124,6 @@ struct lbm_ctx {
 
     void* buf(int i) { return ws + pl.off_buf[i]; }
     double* wall_rho(int i) { return reinterpret_cast<double*>(ws + pl.off_wall + i * pl.wall_bytes); }
-    const WallTable* dev_tables() { return reinterpret_cast<const WallTable*>(ws + pl.off_tab); }
     double* partials() { return reinterpret_cast<double*>(ws + pl.off_part); }
     double* scratch2() { return partials() + (size_t)RED_BLOCKS * 4; }
     template <typename L> L* lam(int i) { return reinterpret_cast<L*>(ws + pl.off_lam[i]); }
@@ -432,6 +432,7 @@ lbm_status lbm_create(const lbm_params* p, void* dev_workspace, size_t bytes, vo
     c->have_prev = false;
     c->lam_cur = 0;
     c->have_lambda = false;
+    c->lam_is_mu = false;
     c->wr_cur = 0;
     c->wr_buf = -1;
     for (int l = 0; l < NPOP; ++l) {
@@ -441,7 +442,6 @@ lbm_status lbm_create(const lbm_params* p, void* dev_workspace, size_t bytes, vo
     }
     set_collide_args(c);
     if (hipMemsetAsync(dev_workspace, 0, pl.total, c->stream) != hipSuccess ||
-        hipMemcpyAsync(c->ws + pl.off_tab, &c->wt, sizeof(WallTable), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
         hipStreamSynchronize(c->stream) != hipSuccess) {
         g_create_error = "workspace initialisation failed";
         delete c;
