@@ -128,6 +128,44 @@ def test_one_reverse_step_with_fp32_lambda(ybc, layout):
     assert e_lam <= 2e-7 and e_tau <= 1e-12
 
 
+@pytest.mark.parametrize("ybc", ["walls", "periodic"])
+@pytest.mark.parametrize("lam_prec", ["fp64", "fp32"])
+def test_two_reverse_steps_match_autograd(ybc, lam_prec):
+    """Two reverse steps in a row: the second takes lambda_1 from what the
+    first stored, so it runs the transposed propagate and bc inside the step
+    kernel (with y-wrap for periodic y).  FP64 lambda: 1e-12 like one step.
+    FP32 lambda: both stored outputs are rounded to FP32 (2^-24 ~ 6e-8 of the
+    largest value each), so lambda_0 is bounded by 5e-7 and d/dtau, whose
+    second term uses the rounded lambda_1, by 1e-6."""
+    lx, ly, g = 24, 20, -1e-3
+    say(f"two adjoint steps {ybc} lambda {lam_prec}")
+    noise = torch.tensor(inputs.population_noise(lx, ly, 41))
+    lam2 = torch.tensor(inputs.population_noise(lx, ly, 42))
+    if lam_prec == "fp32":
+        lam2 = lam2.float().double()
+    lat = Lattice(lx, ly, TAU, g, TB, TT, precision="fp64", ybc=ybc, adjoint=lam_prec, device=DEV)
+    f0 = WT[:, None, None] * (1 + 0.05 * noise)
+    lat.set_pops(f0.to(DEV))
+    st0 = lat.get_state()
+    lat.step(1)
+    st1 = lat.get_state()
+    lat.set_lambda(lam2.to(DEV))
+    dacc = torch.zeros((), dtype=torch.float64, device=DEV)
+    lat.adjoint_step(st1, dacc)
+    lat.adjoint_step(st0, dacc)
+    lam0 = lat.get_lambda()
+    m = TorchD2Q37(lx, ly, g, TB, TT, walls=(ybc == "walls"))
+    f = f0.clone().requires_grad_(True)
+    tau = torch.tensor(TAU, dtype=torch.float64, requires_grad=True)
+    (m.step(m.step(f, tau), tau) * lam2).sum().backward()
+    e_lam, e_tau = rel(lam0, f.grad), rel(dacc, tau.grad)
+    say(f"  lambda {e_lam:.2e}  dtau {e_tau:.2e}")
+    if lam_prec == "fp64":
+        assert e_lam <= 1e-12 and e_tau <= 1e-12
+    else:
+        assert e_lam <= 5e-7 and e_tau <= 1e-6
+
+
 @pytest.mark.parametrize("schedule", ["sqrt", "binomial"])
 @pytest.mark.parametrize("ybc_g", [-2e-3])
 def test_rollout_gradient_matches_autograd(schedule, ybc_g):
