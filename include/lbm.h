@@ -182,8 +182,11 @@ lbm_status lbm_adjoint_seed_temperature(lbm_ctx* ctx, const double* dT);
  * as written by lbm_get_state after n forward steps) and lambda_{n+1} in the
  * context, replaces lambda by lambda_n = (d step / d f_n)^T lambda_{n+1}
  * (collide^T, bc^T and propagate^T) and adds lambda_{n+1} . d step/d tau to
- * *dev_dtau_acc (device FP64 scalar).  Uses the context's population
- * buffers as scratch: set the forward state again before stepping forward. */
+ * *dev_dtau_acc (device FP64 scalar).  The snapshot is only read; the
+ * population buffers are not touched.  Internally the context keeps the
+ * step's collide^T output and applies bc^T and propagate^T when lambda_n is
+ * next read (by the next reverse step, lbm_adjoint_init_rt or
+ * lbm_adjoint_get_lambda), so those reads see lambda_n exactly. */
 lbm_status lbm_adjoint_step(lbm_ctx* ctx, const void* f_n_state, double* dev_dtau_acc);
 /* dP <- dL/dP for the initial state of lbm_init_rt(P, prof), from lambda_0. */
 lbm_status lbm_adjoint_init_rt(lbm_ctx* ctx, const double* P,
