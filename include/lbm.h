@@ -161,6 +161,18 @@ lbm_status lbm_set_pops(lbm_ctx* ctx, const void* src);
  * buffer followed by the densities of its 3 rows next to each wall. */
 lbm_status lbm_get_state(lbm_ctx* ctx, void* dst);
 lbm_status lbm_set_state(lbm_ctx* ctx, const void* src);
+/* One time step (section 5: propagate, bc, collide; evaluated as the pull of
+ * eq. (4) per site, identical to lbm_step) from one snapshot into another:
+ * dst_state <- step(src_state).  Both are device buffers of lbm_state_bytes,
+ * 256-byte aligned, not overlapping, in the format of lbm_get_state (dst
+ * receives the new state's wall densities too, so it can serve as the next
+ * source or as an lbm_adjoint_step snapshot).  The sites and wall densities
+ * of src_state are only read; its padding (y ghost rows, x halo columns) is
+ * refreshed in place when the boundary mode needs it.  The context's own
+ * population buffers are not touched.  Lets a checkpointed replay run from
+ * snapshot to snapshot instead of stepping the context and copying its state
+ * out. */
+lbm_status lbm_step_state(lbm_ctx* ctx, void* src_state, void* dst_state);
 /* Lattice totals of the collision invariants, accumulated in FP64 with a
  * fixed reduction order (bitwise reproducible): out4 = {sum rho, sum j_x,
  * sum j_y, sum E}, E = sum_l |xi_l|^2 f_l.  dev_out4: device FP64 [4]. */

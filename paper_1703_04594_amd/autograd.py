@@ -62,7 +62,8 @@ class RTRollout(torch.autograd.Function):
         fwd, bwd = sch.split_at_first_adjoint()
         dacc = torch.zeros((), dtype=torch.float64, device=P.device)
         ex = checkpoint.Executor(lat, dacc)
-        ex.run(fwd)          # ends holding f_{N-1}
+        ex.run(fwd)
+        ex.materialize()     # the lattice holds f_{N-1}
         lat.step(1)          # f_N
         T = lat.macros()[3]
         ctx.lat, ctx.ex, ctx.bwd, ctx.P, ctx.cfg = lat, ex, bwd, P, cfg

@@ -221,15 +221,28 @@ def binomial_forward_steps(l: int, s: int) -> int:
 
 
 class Executor:
-    """Runs schedule actions against a Lattice (with adjoint buffers)."""
+    """Runs schedule actions against a Lattice (with adjoint buffers).
 
-    def __init__(self, lat, dtau_acc):
+    The current forward state lives either in the lattice or in a slot.  A
+    restore only moves that marker; an advance by one step followed by a
+    store of the result is run as one step from the current slot straight
+    into the target slot (Lattice.step_state), so a replayed segment goes
+    from snapshot to snapshot without copying states in or out of the
+    lattice.  Results are bitwise those of the plain sequence (set_state,
+    step, get_state)."""
+
+    LATTICE = -1
+
+    def __init__(self, lat, dtau_acc, chain: bool = True):
         self.lat = lat
         self.dtau = dtau_acc
+        self.chain = chain
         self.slots: dict[int, object] = {}
+        self.where = Executor.LATTICE
         self.forward_steps = 0
         self.adjoint_steps = 0
         self.peak_slots = 0
+        self.state_copies = 0
 
     def _slot(self, i):
         if i not in self.slots:
@@ -237,16 +250,45 @@ class Executor:
             self.peak_slots = max(self.peak_slots, len(self.slots))
         return self.slots[i]
 
+    def materialize(self):
+        """Make the lattice hold the current forward state."""
+        if self.where != Executor.LATTICE:
+            self.lat.set_state(self.slots[self.where])
+            self.state_copies += 1
+            self.where = Executor.LATTICE
+
     def run(self, actions):
-        for act in actions:
+        i = 0
+        while i < len(actions):
+            act = actions[i]
             op = act[0]
             if op == "advance":
-                self.lat.step(act[2] - act[1])
-                self.forward_steps += act[2] - act[1]
+                a, b = act[1], act[2]
+                nxt = actions[i + 1] if i + 1 < len(actions) else None
+                if (self.chain and self.where != Executor.LATTICE and b - a == 1 and nxt is not None
+                        and nxt[0] == "store" and nxt[1] == b and nxt[2] != self.where):
+                    self.lat.step_state(self.slots[self.where], self._slot(nxt[2]))
+                    self.where = nxt[2]
+                    self.forward_steps += 1
+                    i += 2
+                    continue
+                self.materialize()
+                self.lat.step(b - a)
+                self.forward_steps += b - a
             elif op == "store":
-                self.lat.get_state(self._slot(act[2]))
+                if self.where == Executor.LATTICE:
+                    self.lat.get_state(self._slot(act[2]))
+                    self.state_copies += 1
+                elif self.where != act[2]:
+                    self._slot(act[2]).copy_(self.slots[self.where])
+                    self.state_copies += 1
             elif op == "restore":
-                self.lat.set_state(self.slots[act[2]])
+                if self.chain:
+                    self.where = act[2]
+                else:
+                    self.lat.set_state(self.slots[act[2]])
+                    self.state_copies += 1
+                    self.where = Executor.LATTICE
             elif op == "adjoint":
                 self.lat.adjoint_step(self.slots[act[2]], self.dtau)
                 self.adjoint_steps += 1
@@ -254,3 +296,4 @@ class Executor:
                 pass   # slots are kept allocated and reused by index
             else:
                 raise ValueError(op)
+            i += 1

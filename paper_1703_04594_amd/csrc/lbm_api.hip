@@ -392,6 +392,31 @@ lbm_status do_get_state(lbm_ctx* c, char* dst)
     return LBM_OK;
 }
 
+// One fused step from snapshot src into snapshot dst (both buffer + wall
+// densities); the context's own buffers and wall tables are not touched.
+template <typename S>
+lbm_status do_step_state(lbm_ctx* c, char* src, char* dst)
+{
+    const Geo& g = c->pl.geo;
+    S* sb = (S*)src;
+    S* db = (S*)dst;
+    lbm_status s = launch_pre_stream<S>(c, sb);   // padding of the source only
+    if (s) return s;
+    const bool walls = c->p.ybc == LBM_Y_WALLS;
+    const bool wrap = c->p.xmode == LBM_X_WRAP;
+    const double* wr = walls ? (const double*)(src + c->pl.buf_bytes) : nullptr;
+    double* wo = walls ? (double*)(dst + c->pl.buf_bytes) : nullptr;
+    if (wrap && walls)
+        hipLaunchKernelGGL((k_step_fused<S, true, true>), site_grid(g), dim3(SITE_THREADS), 0, c->stream, sb, db, g, c->cargs, wr, c->wt, wo);
+    else if (wrap)
+        hipLaunchKernelGGL((k_step_fused<S, true, false>), site_grid(g), dim3(SITE_THREADS), 0, c->stream, sb, db, g, c->cargs, wr, c->wt, wo);
+    else if (walls)
+        hipLaunchKernelGGL((k_step_fused<S, false, true>), site_grid(g), dim3(SITE_THREADS), 0, c->stream, sb, db, g, c->cargs, wr, c->wt, wo);
+    else
+        hipLaunchKernelGGL((k_step_fused<S, false, false>), site_grid(g), dim3(SITE_THREADS), 0, c->stream, sb, db, g, c->cargs, wr, c->wt, wo);
+    return check_launch(c, "step_state");
+}
+
 template <typename S>
 lbm_status do_conservation(lbm_ctx* c, double* out4)
 {
@@ -548,6 +573,19 @@ lbm_status lbm_set_state(lbm_ctx* c, const void* src)
         c->wr_buf = c->cur;
     }
     return LBM_OK;
+}
+
+lbm_status lbm_step_state(lbm_ctx* c, void* src_state, void* dst_state)
+{
+    if (!c) return LBM_ERR_INVALID;
+    if (!src_state || !dst_state) return fail(c, LBM_ERR_INVALID, "step_state: NULL");
+    if (((uintptr_t)src_state | (uintptr_t)dst_state) % ALIGN != 0)
+        return fail(c, LBM_ERR_INVALID, "step_state: snapshots must be 256-byte aligned");
+    const char* a = (const char*)src_state;
+    const char* b = (const char*)dst_state;
+    const size_t n = c->pl.state_bytes;
+    if (a < b + n && b < a + n) return fail(c, LBM_ERR_INVALID, "step_state: snapshots overlap");
+    return DISPATCH(c, do_step_state, (char*)src_state, (char*)dst_state);
 }
 
 lbm_status lbm_conservation(lbm_ctx* c, double* dev_out4)

@@ -95,6 +95,7 @@ def lib() -> ctypes.CDLL:
         getattr(L, n).argtypes = [vp, vp]
     L.lbm_loss_temperature.argtypes = [vp, vp, vp]
     L.lbm_adjoint_step.argtypes = [vp, vp, vp]
+    L.lbm_step_state.argtypes = [vp, vp, vp]
     L.lbm_adjoint_init_rt.argtypes = [vp, vp, ctypes.POINTER(RtProfileC), vp]
     L.lbm_last_error.argtypes = [vp]
     L.lbm_last_error.restype = ctypes.c_char_p
@@ -105,7 +106,7 @@ def lib() -> ctypes.CDLL:
     L.lbm_scale_c.restype = ctypes.c_double
     for n in ("lbm_create", "lbm_set_tau", "lbm_init", "lbm_init_rt", "lbm_propagate", "lbm_bc",
               "lbm_collide", "lbm_step", "lbm_get_macros", "lbm_get_pops", "lbm_set_pops",
-              "lbm_get_state", "lbm_set_state", "lbm_conservation", "lbm_loss_temperature",
+              "lbm_get_state", "lbm_set_state", "lbm_step_state", "lbm_conservation", "lbm_loss_temperature",
               "lbm_adjoint_seed_temperature", "lbm_adjoint_step", "lbm_adjoint_init_rt",
               "lbm_adjoint_get_lambda", "lbm_adjoint_set_lambda", "lbm_sync"):
         getattr(L, n).restype = st
@@ -254,6 +255,13 @@ class Lattice:
     def set_state(self, s: torch.Tensor):
         p = _ptr(s, torch.uint8, (self.state_bytes,), self.device)
         self._check(self.L.lbm_set_state(self.h, ctypes.c_void_p(p)), "set_state")
+
+    def step_state(self, src: torch.Tensor, dst: torch.Tensor):
+        """dst <- one step from the snapshot src (lbm_step_state); the
+        lattice's own state is untouched."""
+        ps = _ptr(src, torch.uint8, (self.state_bytes,), self.device)
+        pd = _ptr(dst, torch.uint8, (self.state_bytes,), self.device)
+        self._check(self.L.lbm_step_state(self.h, ctypes.c_void_p(ps), ctypes.c_void_p(pd)), "step_state")
 
     def conservation(self) -> torch.Tensor:
         out = torch.empty(4, dtype=torch.float64, device=self.device)

@@ -23,7 +23,7 @@ def declared_functions():
 def test_every_declared_symbol_is_exported():
     L = lbm.lib()
     names = declared_functions()
-    assert len(names) == 28
+    assert len(names) == 29
     missing = [n for n in names if not hasattr(L, n)]
     assert not missing, missing
 
@@ -54,6 +54,7 @@ def test_host_side_validation():
     assert L.lbm_create(ctypes.byref(good), ctypes.c_void_p(4096), n - 1, None, ctypes.byref(h)) == 2
     assert L.lbm_create(ctypes.byref(good), ctypes.c_void_p(4096 + 8), n, None, ctypes.byref(h)) == 1
     assert not h.value
+    assert L.lbm_step_state(None, None, None) == 1
     # FP32 storage halves the population buffers; the adjoint adds FP64 lambda
     p32 = lbm.make_params(64, 48, 0.7, precision="fp32")
     assert lbm.workspace_bytes(p32) < n

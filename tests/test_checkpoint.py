@@ -30,6 +30,14 @@ def test_binomial_repetition_count_matches_beta():
             assert ck.repetitions(l + 1, c - 1) == r + 1
 
 
+class FakeState:
+    def __init__(self):
+        self.n = None
+
+    def copy_(self, other):
+        self.n = other.n
+
+
 class FakeLattice:
     """State = the step index it holds."""
 
@@ -39,32 +47,39 @@ class FakeLattice:
         self.steps = 0
 
     def new_state(self):
-        return [None]
+        return FakeState()
 
     def get_state(self, out):
-        out[0] = self.n
+        out.n = self.n
         return out
 
     def set_state(self, s):
-        self.n = s[0]
+        self.n = s.n
 
     def step(self, k):
         self.n += k
         self.steps += k
 
+    def step_state(self, src, dst):
+        assert src is not dst
+        dst.n = src.n + 1
+        self.steps += 1
+
     def adjoint_step(self, s, dacc):
-        assert s[0] == self.expect, (s[0], self.expect)
+        assert s.n == self.expect, (s.n, self.expect)
         self.expect -= 1
 
 
 @pytest.mark.parametrize("N", [1, 2, 7, 50, 257])
 @pytest.mark.parametrize("kind", ["sqrt", "binomial2", "binomial5"])
-def test_schedules_feed_every_state_in_reverse_order(N, kind):
+@pytest.mark.parametrize("chain", [False, True])
+def test_schedules_feed_every_state_in_reverse_order(N, kind, chain):
     sch = ck.sqrt_schedule(N) if kind == "sqrt" else ck.binomial_schedule(N, int(kind[-1]))
     fwd, bwd = sch.split_at_first_adjoint()
     lat = FakeLattice()
-    ex = ck.Executor(lat, None)
+    ex = ck.Executor(lat, None, chain=chain)
     ex.run(fwd)
+    ex.materialize()
     assert lat.n == N - 1          # the forward prefix ends holding f_{N-1}
     lat.step(1)                    # the rollout's last step, to f_N
     lat.expect = N - 1
@@ -72,6 +87,28 @@ def test_schedules_feed_every_state_in_reverse_order(N, kind):
     assert lat.expect == -1        # all N reverse steps, each with its own f_n
     assert ex.adjoint_steps == N
     assert ex.forward_steps == sch.forward_steps()
+    assert lat.steps == sch.forward_steps() + 1
+
+
+def test_chaining_removes_most_state_copies():
+    """Replayed segments run slot to slot: the 10,000-step binomial schedule
+    with 100 slots copies states in or out of the lattice only for the first
+    sweep and for multi-step advances."""
+    sch = ck.binomial_schedule(10000, 100)
+    copies = {}
+    for chain in (False, True):
+        fwd, bwd = sch.split_at_first_adjoint()
+        lat = FakeLattice()
+        ex = ck.Executor(lat, None, chain=chain)
+        ex.run(fwd)
+        ex.materialize()
+        lat.step(1)
+        lat.expect = 10000 - 1
+        ex.run(bwd)
+        assert lat.expect == -1
+        copies[chain] = ex.state_copies
+    assert copies[False] >= 10000
+    assert copies[True] < copies[False] / 5
 
 
 def test_sqrt_schedule_memory_and_cost():

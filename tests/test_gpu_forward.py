@@ -167,6 +167,43 @@ def test_ragged_lattices(step, lx, ly, ybc):
     assert err <= 1e-12, (err)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("ybc,xmode", [("walls", "wrap"), ("periodic", "wrap"), ("walls", "halo")])
+def test_step_state_equals_step(precision, ybc, xmode):
+    """lbm_step_state (snapshot to snapshot) gives bitwise the state that
+    set_state + lbm_step + get_state gives, chained over two steps, with the
+    same wall densities, and leaves the context's own state alone;
+    overlapping snapshots are refused."""
+    lx, ly = 40, 33
+    say(f"step_state {precision} {ybc} {xmode}")
+    P = inputs.rt_perturbation(lx, ly, 5)
+    lat = Lattice(lx, ly, TAU, G, TB, TT, precision=precision, ybc=ybc, xmode=xmode, step="fused", device=DEV)
+    lat.init_rt(tg(P))
+    lat.step(3)
+    s0 = lat.get_state()
+    f_before = lat.get_pops().clone()
+    s1, s2 = lat.new_state(), lat.new_state()
+    lat.step_state(s0, s1)
+    lat.step_state(s1, s2)
+    assert torch.equal(lat.get_pops(), f_before)          # the context's state is untouched
+    ref = Lattice(lx, ly, TAU, G, TB, TT, precision=precision, ybc=ybc, xmode=xmode, step="fused", device=DEV)
+    ref.set_state(s0)
+    ref.step(1)
+    r1 = ref.get_state()
+    ref.step(1)
+    r2 = ref.get_state()
+    wall = 6 * lx * 8                                     # wall densities after the buffer
+    tail0 = lat.state_bytes - ((wall + 255) // 256) * 256
+    for got, want in ((s1, r1), (s2, r2)):
+        ref.set_state(want)
+        lat.set_state(got)
+        assert torch.equal(lat.get_pops(), ref.get_pops())
+        if ybc == "walls":
+            assert torch.equal(got[tail0:tail0 + wall], want[tail0:tail0 + wall])
+    with pytest.raises(Exception):
+        lat.step_state(s1, s1)                            # overlapping snapshots
+
+
 def test_split_calls_equal_step():
     lx, ly = 50, 40
     f0 = random_state(lx, ly, 9)
