@@ -404,6 +404,51 @@ def cpu_oracle_serial(lx=256, ly=128, n=50):
             "seconds": round(dt, 3), "sample": f"{n} FP64 steps of the {lx}x{ly} RT lattice, serial build"}
 
 
+def layout_study(lx=2160, ly=8192, reps=20):
+    """Per-kernel times of the FP64 step on the paper's 2160x8192 lattice
+    (its Table 2 experiment) for each layout the library supports: planes
+    (structure of arrays) and columns (the 37 segments of a column
+    together).  HIP events over `reps` back-to-back launches per kernel."""
+    import torch
+
+    from paper_1703_04594_amd import inputs
+    from paper_1703_04594_amd.lbm import Lattice
+
+    dev = "cuda:0"
+    P = torch.tensor(inputs.rt_perturbation(lx, ly, 1), device=dev)
+    sites = lx * ly
+    nbytes = 2 * 37 * 8 * sites
+    out = {"lattice": f"{lx}x{ly}", "precision": "fp64", "layouts": {}}
+    for layout in ("planes", "columns"):
+        row = {}
+        lat = Lattice(lx, ly, 0.7, -1e-5, 4 / 3, 2 / 3, precision="fp64", step="split", layout=layout, device=dev)
+        lat.init_rt(P)
+        s = lat.stream
+        lat.step(2)
+        t_prop = time_launches(lat.propagate, s, reps)
+        t_bc = time_launches(lat.bc, s, reps)
+        t_coll = time_launches(lat.collide, s, reps)
+        t_split = time_launches(lambda: lat.step(1), s, reps)
+        del lat
+        torch.cuda.empty_cache()
+        lat = Lattice(lx, ly, 0.7, -1e-5, 4 / 3, 2 / 3, precision="fp64", step="fused", layout=layout, device=dev)
+        lat.init_rt(P)
+        lat.step(2)
+        t_fused = time_launches(lambda: lat.step(1), lat.stream, reps)
+        del lat
+        torch.cuda.empty_cache()
+        for name, t in (("propagate", t_prop), ("bc", t_bc), ("collide", t_coll), ("step_split", t_split),
+                        ("step_fused", t_fused)):
+            row[name + "_ms"] = round(t * 1e3, 4)
+        row["propagate_GBps"] = round(nbytes / t_prop / 1e9, 1)
+        row["collide_GBps"] = round(nbytes / t_coll / 1e9, 1)
+        row["split_mlups"] = round(sites / t_split / 1e6, 1)
+        row["fused_mlups"] = round(sites / t_fused / 1e6, 1)
+        out["layouts"][layout] = row
+        log(f"bench: layout {layout}: {row}")
+    return out
+
+
 def profile_workload(args):
     """Short fixed sequence for rocprofv3 runs: a plain device copy of known
     size (calibrates the HBM byte counters), the reference copy of one
@@ -463,6 +508,8 @@ def main():
                     help="skip the FP32 accuracy and adjoint-at-scale measurements")
     ap.add_argument("--profile", action="store_true",
                     help="run the short fixed kernel sequence used under rocprofv3")
+    ap.add_argument("--layout-study", action="store_true",
+                    help="per-kernel FP64 times on the 2160x8192 lattice for each layout (one JSON line)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: runs on one GPU only; multi-GPU X-slab sharding is not implemented",
@@ -470,6 +517,9 @@ def main():
         sys.exit(2)
     if args.profile:
         profile_workload(args)
+        return
+    if args.layout_study:
+        print(json.dumps({"layout_study": layout_study()}), flush=True)
         return
     res = run(args)
     if not args.skip_reports:

@@ -362,8 +362,9 @@ __global__ __launch_bounds__(SITE_THREADS) void k_lambda_to_canon(const L* __res
 template <typename L>
 __global__ __launch_bounds__(256) void k_lambda_from_canon(L* __restrict__ buf, const double* __restrict__ canon, Geo g)
 {
-    const int l = blockIdx.z, x = blockIdx.y;
-    const int y = blockIdx.x * 256 + threadIdx.x;
+    const int nyb = (g.ly + 255) / 256;
+    const int l = blockIdx.y, x = (int)(blockIdx.x / (unsigned)nyb);
+    const int y = (int)(blockIdx.x % (unsigned)nyb) * 256 + threadIdx.x;
     if (y >= g.ly) return;
     buf[(size_t)l * g.ps + g.origin + (long long)x * g.cs + y] = (L)canon[((size_t)l * g.lx + x) * g.ly + y];
 }

@@ -55,9 +55,12 @@ def test_host_side_validation():
     assert L.lbm_create(ctypes.byref(good), ctypes.c_void_p(4096 + 8), n, None, ctypes.byref(h)) == 1
     assert not h.value
     assert L.lbm_step_state(None, None, None) == 1
-    # FP32 storage halves the population buffers; the adjoint adds FP64 lambda
-    p32 = lbm.make_params(64, 48, 0.7, precision="fp32")
-    assert lbm.workspace_bytes(p32) < n
+    # FP32 storage about halves the population buffers (on a lattice tall
+    # enough for the ghost rows and padding not to dominate); the adjoint adds
+    # FP64 lambda
+    n64 = lbm.workspace_bytes(lbm.make_params(64, 1000, 0.7))
+    n32 = lbm.workspace_bytes(lbm.make_params(64, 1000, 0.7, precision="fp32"))
+    assert n32 < 0.6 * n64
     assert lbm.workspace_bytes(lbm.make_params(64, 48, 0.7, adjoint=True)) > n
 
 

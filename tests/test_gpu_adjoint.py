@@ -287,3 +287,18 @@ def test_binomial_and_sqrt_give_bitwise_equal_gradients():
         out.append((Pg.grad.clone(), tg.grad.clone(), cfg.stats))
     assert torch.equal(out[0][0], out[1][0]) and torch.equal(out[0][1], out[1][1])
     say(f"  sqrt {out[0][2]}  binomial {out[1][2]}")
+
+
+@pytest.mark.parametrize("lam", ["fp64", "fp32"])
+def test_lambda_round_trip_wider_than_grid_y(lam):
+    """70000x8: more columns than the 65,535 blocks of a grid's y dimension.
+    set_lambda / get_lambda return lambda unchanged (FP32 storage: rounded
+    once to FP32)."""
+    lx, ly = 70000, 8
+    say(f"lambda round trip {lam} {lx}x{ly}")
+    lat = Lattice(lx, ly, TAU, precision="fp32", adjoint=lam, device=DEV)
+    lam1 = torch.tensor(inputs.population_noise(lx, ly, 33))
+    if lam == "fp32":
+        lam1 = lam1.float().double()
+    lat.set_lambda(lam1.to(DEV))
+    assert torch.equal(lat.get_lambda().cpu(), lam1)

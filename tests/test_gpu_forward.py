@@ -55,10 +55,36 @@ def test_propagate_is_the_bitwise_permutation(lx, ly, xmode, ybc, layout):
 
 
 def test_propagate_multi_row_grid_is_bitwise():
-    """2048x8192 FP64: 1,212,416 propagate workgroups, more than one grid row
-    of 2^20, so the launch takes its 2-D form with a partial last row."""
-    lx, ly = 2048, 8192
+    """460000x16 FP64: one 384-byte propagate chunk per segment, so
+    37 x 460000 = 17,020,000 workgroups, more than one grid row of 2^24 - 1: the
+    launch takes its 2-D form with a partial last row.  The lattice is also
+    wider than the 65,535 blocks of a grid's y dimension, which the
+    canonical-order copies (set_pops, get_pops) must not depend on."""
+    lx, ly = 460000, 16
+    assert 37 * lx > (1 << 32) // 256
     say(f"propagate permutation {lx}x{ly} (multi-row grid)")
+    t = tagged(lx, ly)
+    lat = Lattice(lx, ly, TAU, device=DEV)
+    lat.set_pops(tg(t))
+    assert np.array_equal(lat.get_pops().cpu().numpy(), t)
+    lat.propagate()
+    got = lat.get_pops().cpu().numpy()
+    del lat
+    torch.cuda.empty_cache()
+    ref = oracle.RefLattice(lx, ly, TAU)
+    ref.set_pops(t)
+    del t
+    ref.propagate()
+    want = ref.get_pops()
+    ok = ~np.isnan(want)
+    assert np.array_equal(got[ok], want[ok])
+
+
+def test_propagate_segment_stride_1024x8192_is_bitwise():
+    """ly = 8192 in FP64 is the shape whose column segments get one extra
+    128-byte line (an odd line count); propagate stays a pure permutation."""
+    lx, ly = 1024, 8192
+    say(f"propagate permutation {lx}x{ly}")
     t = tagged(lx, ly)
     lat = Lattice(lx, ly, TAU, device=DEV)
     lat.set_pops(tg(t))
