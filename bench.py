@@ -406,9 +406,11 @@ def cpu_oracle_serial(lx=256, ly=128, n=50):
 
 def layout_study(lx=2160, ly=8192, reps=20):
     """Per-kernel times of the FP64 step on the paper's 2160x8192 lattice
-    (its Table 2 experiment) for each layout the library supports: planes
-    (structure of arrays) and columns (the 37 segments of a column
-    together).  HIP events over `reps` back-to-back launches per kernel."""
+    (its Table 2 experiment): for each layout the library's step supports,
+    planes (structure of arrays) and columns (the 37 segments of a column
+    together), and for the paper's four layouts (AOS, SOA, CSOA and CAOSOA,
+    cluster widths 8-64) with the study kernels.  HIP events over `reps`
+    back-to-back launches per kernel."""
     import torch
 
     from paper_1703_04594_amd import inputs
@@ -446,6 +448,34 @@ def layout_study(lx=2160, ly=8192, reps=20):
         row["fused_mlups"] = round(sites / t_fused / 1e6, 1)
         out["layouts"][layout] = row
         log(f"bench: layout {layout}: {row}")
+
+    # The paper's four layouts (section 4), with the library's generic study
+    # kernels (one element per thread in propagate, one site per thread in
+    # collide; periodic in x and y), on an RT state of the same lattice.
+    from paper_1703_04594_amd import lbm as L
+    lat = Lattice(lx, ly, 0.7, -1e-5, 4 / 3, 2 / 3, precision="fp64", step="fused", device=dev)
+    lat.init_rt(P)
+    lat.step(2)
+    f = lat.get_pops()
+    del lat
+    torch.cuda.empty_cache()
+    s = torch.cuda.current_stream()
+    out["study_layouts"] = {}
+    for layout, vl in [("aos", 1), ("soa", 1)] + [(k, v) for k in ("csoa", "caosoa") for v in (8, 16, 32, 64)]:
+        buf = L.study_pack(layout, vl, f)
+        dst = torch.empty_like(buf)
+        prop = lambda: L.study_propagate(layout, vl, lx, ly, buf, dst)     # noqa: E731
+        coll = lambda: L.study_collide(layout, vl, lx, ly, 0.7, -1e-5, buf)  # noqa: E731
+        prop()
+        coll()
+        t_prop = time_launches(prop, s, reps)
+        t_coll = time_launches(coll, s, reps)
+        del buf, dst
+        name = layout if layout in ("aos", "soa") else f"{layout}_vl{vl}"
+        row = {"propagate_ms": round(t_prop * 1e3, 4), "collide_ms": round(t_coll * 1e3, 4),
+               "propagate_GBps": round(nbytes / t_prop / 1e9, 1), "collide_GBps": round(nbytes / t_coll / 1e9, 1)}
+        out["study_layouts"][name] = row
+        log(f"bench: study layout {name}: {row}")
     return out
 
 

@@ -207,12 +207,47 @@ lbm_status lbm_adjoint_init_rt(lbm_ctx* ctx, const double* P,
 lbm_status lbm_adjoint_get_lambda(lbm_ctx* ctx, double* dst);
 lbm_status lbm_adjoint_set_lambda(lbm_ctx* ctx, const double* src);
 
+/* ---- layout study ---------------------------------------------------------- */
+/* The four data layouts compared in section 4 (Table 2: propagate and collide
+ * on a 2160 x 8192 lattice), for timing those two kernels on each.  These
+ * calls are stateless and separate from contexts: FP64 populations of an
+ * lx x ly lattice, periodic in x and y, no halos, no padding, no walls.
+ * Population l of site (x, y) is element
+ *   AOS     (x ly + y) 37 + l              all populations of a site together
+ *   SOA     (l lx + x) ly + y              one array per population
+ *   CSOA    ((l lx + x) M + i) VL + k      y = k M + i, M = ly / VL
+ *   CAOSOA  ((x M + i) 37 + l) VL + k      y = k M + i
+ * CSOA and CAOSOA split each column into VL partitions of M rows; a cluster
+ * of VL elements holds the rows at the same offset i in every partition, so
+ * a hop in y moves whole clusters (the clustered layouts of section 4, with VL
+ * the cluster width).  AOS and SOA take vl = 1; CSOA and CAOSOA take
+ * vl = 1, 2, 4, ..., 64 with ly a multiple of vl and ly / vl >= 3.  lx, ly
+ * >= 7 and lx ly <= 2^26.  All buffers are device pointers to
+ * lbm_study_bytes() bytes (canonical arrays: FP64 [37][lx][ly], the same
+ * size); calls enqueue on the given HIP stream (NULL: the null stream) and
+ * return at once.  Errors: LBM_ERR_INVALID / LBM_ERR_SIZE for bad arguments
+ * (nothing is launched), LBM_ERR_HIP for a failed launch; the message is
+ * lbm_last_error(NULL). */
+typedef enum { LBM_STUDY_AOS = 0, LBM_STUDY_SOA = 1, LBM_STUDY_CSOA = 2, LBM_STUDY_CAOSOA = 3 } lbm_study_layout;
+/* Bytes of one population buffer in that layout; 0 if the arguments are invalid. */
+size_t lbm_study_bytes(int layout, int vl, int lx, int ly);
+/* canonical [37][lx][ly] -> layout buffer, and back. */
+lbm_status lbm_study_pack(int layout, int vl, int lx, int ly, const double* canon, double* buf, void* hip_stream);
+lbm_status lbm_study_unpack(int layout, int vl, int lx, int ly, const double* buf, double* canon, void* hip_stream);
+/* propagate (eq. (4), pull form): dst_l(x, y) = src_l(x - e_x, y - e_y), both
+ * coordinates periodic.  src and dst are distinct buffers of the layout. */
+lbm_status lbm_study_propagate(int layout, int vl, int lx, int ly, const double* src, double* dst, void* hip_stream);
+/* collide (eq. (2) with the equilibrium and gravity of lbm_collide), in place
+ * on a buffer of the layout; tau > 0.5. */
+lbm_status lbm_study_collide(int layout, int vl, int lx, int ly, double tau, double g_y, double* buf,
+                             void* hip_stream);
+
 /* ---- misc ------------------------------------------------------------------ */
 
 /* Waits for the context's stream; LBM_ERR_HIP if queued work failed. */
 lbm_status lbm_sync(lbm_ctx* ctx);
 /* Message of the last error on this context ("" if none); NULL ctx: last
- * error of lbm_create on this thread. */
+ * error of lbm_create or of an lbm_study_* call on this thread. */
 const char* lbm_last_error(const lbm_ctx* ctx);
 /* Canonical population order (host arrays of 37). */
 void lbm_velocity_table(int8_t ex[LBM_NPOP], int8_t ey[LBM_NPOP]);

@@ -628,3 +628,4 @@ double lbm_scale_c(void) { return C; }
 }  // extern "C"
 
 #include "lbm_adjoint_api.inc"
+#include "lbm_layouts_api.inc"

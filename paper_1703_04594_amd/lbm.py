@@ -104,6 +104,14 @@ def lib() -> ctypes.CDLL:
     L.lbm_weights.argtypes = [ctypes.POINTER(ctypes.c_double)]
     L.lbm_weights.restype = None
     L.lbm_scale_c.restype = ctypes.c_double
+    ci = ctypes.c_int
+    L.lbm_study_bytes.argtypes = [ci, ci, ci, ci]
+    L.lbm_study_bytes.restype = ctypes.c_size_t
+    for n in ("lbm_study_pack", "lbm_study_unpack", "lbm_study_propagate"):
+        getattr(L, n).argtypes = [ci, ci, ci, ci, vp, vp, vp]
+        getattr(L, n).restype = st
+    L.lbm_study_collide.argtypes = [ci, ci, ci, ci, d, d, vp, vp]
+    L.lbm_study_collide.restype = st
     for n in ("lbm_create", "lbm_set_tau", "lbm_init", "lbm_init_rt", "lbm_propagate", "lbm_bc",
               "lbm_collide", "lbm_step", "lbm_get_macros", "lbm_get_pops", "lbm_set_pops",
               "lbm_get_state", "lbm_set_state", "lbm_step_state", "lbm_conservation", "lbm_loss_temperature",
@@ -301,3 +309,66 @@ class Lattice:
 
     def sync(self):
         self._check(self.L.lbm_sync(self.h), "sync")
+
+
+# ---------------------------------------------------------------------------
+# Layout study (section 4, Table 2): stateless propagate / collide on FP64
+# buffers in one of the paper's four layouts, periodic in x and y.
+# ---------------------------------------------------------------------------
+STUDY_LAYOUTS = {"aos": 0, "soa": 1, "csoa": 2, "caosoa": 3}
+
+
+def _study_args(layout: str, vl: int, lx: int, ly: int):
+    if layout not in STUDY_LAYOUTS:
+        raise ValueError(f"unknown study layout {layout!r}")
+    return STUDY_LAYOUTS[layout], int(vl), int(lx), int(ly)
+
+
+def _study_check(st: int, what: str):
+    if st != 0:
+        raise LBMError(f"{what}: {lib().lbm_last_error(None).decode()} (status {st})")
+
+
+def study_bytes(layout: str, vl: int, lx: int, ly: int) -> int:
+    """Bytes of one population buffer; 0 for an invalid combination."""
+    return int(lib().lbm_study_bytes(*_study_args(layout, vl, lx, ly)))
+
+
+def _stream(t: torch.Tensor) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def study_pack(layout: str, vl: int, canon: torch.Tensor) -> torch.Tensor:
+    """canonical FP64 (37, lx, ly) -> new flat FP64 buffer in the layout."""
+    _, lx, ly = canon.shape
+    a = _study_args(layout, vl, lx, ly)
+    _ptr(canon, torch.float64, (NPOP, lx, ly), canon.device)
+    buf = torch.empty(NPOP * lx * ly, dtype=torch.float64, device=canon.device)
+    _study_check(lib().lbm_study_pack(*a, ctypes.c_void_p(canon.data_ptr()), ctypes.c_void_p(buf.data_ptr()),
+                                      _stream(canon)), "study_pack")
+    return buf
+
+
+def study_unpack(layout: str, vl: int, lx: int, ly: int, buf: torch.Tensor) -> torch.Tensor:
+    """flat FP64 buffer in the layout -> new canonical FP64 (37, lx, ly)."""
+    a = _study_args(layout, vl, lx, ly)
+    _ptr(buf, torch.float64, (NPOP * lx * ly,), buf.device)
+    out = torch.empty((NPOP, lx, ly), dtype=torch.float64, device=buf.device)
+    _study_check(lib().lbm_study_unpack(*a, ctypes.c_void_p(buf.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                        _stream(buf)), "study_unpack")
+    return out
+
+
+def study_propagate(layout: str, vl: int, lx: int, ly: int, src: torch.Tensor, dst: torch.Tensor):
+    a = _study_args(layout, vl, lx, ly)
+    _ptr(src, torch.float64, (NPOP * lx * ly,), src.device)
+    _ptr(dst, torch.float64, (NPOP * lx * ly,), src.device)
+    _study_check(lib().lbm_study_propagate(*a, ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
+                                           _stream(src)), "study_propagate")
+
+
+def study_collide(layout: str, vl: int, lx: int, ly: int, tau: float, g_y: float, buf: torch.Tensor):
+    a = _study_args(layout, vl, lx, ly)
+    _ptr(buf, torch.float64, (NPOP * lx * ly,), buf.device)
+    _study_check(lib().lbm_study_collide(*a, float(tau), float(g_y), ctypes.c_void_p(buf.data_ptr()),
+                                         _stream(buf)), "study_collide")

@@ -23,7 +23,7 @@ def declared_functions():
 def test_every_declared_symbol_is_exported():
     L = lbm.lib()
     names = declared_functions()
-    assert len(names) == 29
+    assert len(names) == 34
     missing = [n for n in names if not hasattr(L, n)]
     assert not missing, missing
 
@@ -84,3 +84,37 @@ def test_reference_copy_library_rejects_bad_arguments():
     assert f(0x1008, 0x100000, 32, 2048, None) == 1            # misaligned source
     assert f(0x1000, 0x1010, 64, 2048, None) == 1              # overlapping ranges
     assert f(0x1000, 0x100000, 64, 3000, None) == 1            # unsupported workgroup size
+
+
+def test_layout_study_validates_arguments():
+    """Sizes of the four layouts, and every invalid combination refused on
+    the host before anything is launched (status 1 or 2, a message)."""
+    L = lbm.lib()
+    n = 37 * 64 * 96 * 8
+    for layout, vl in (("aos", 1), ("soa", 1), ("csoa", 1), ("csoa", 8), ("caosoa", 32)):
+        assert lbm.study_bytes(layout, vl, 64, 96) == n
+    for layout, vl, lx, ly in (("aos", 2, 64, 96),      # AOS and SOA take vl = 1
+                               ("soa", 4, 64, 96),
+                               ("csoa", 3, 64, 96),     # not a power of two
+                               ("csoa", 128, 64, 1024),  # wider than a wave
+                               ("caosoa", 64, 64, 96),  # ly not a multiple of vl
+                               ("csoa", 32, 64, 64),    # ly / vl < 3
+                               ("csoa", 8, 6, 96),      # lx < 7
+                               ("soa", 1, 1 << 14, 1 << 13)):   # more than 2^26 sites
+        assert lbm.study_bytes(layout, vl, lx, ly) == 0, (layout, vl, lx, ly)
+    assert L.lbm_study_bytes(4, 1, 64, 96) == 0
+    fake = ctypes.c_void_p(4096)
+    assert L.lbm_study_propagate(1, 1, 64, 96, None, fake, None) == 1
+    assert b"NULL" in L.lbm_last_error(None)
+    assert L.lbm_study_propagate(1, 1, 64, 96, fake, fake, None) == 1
+    assert b"differ" in L.lbm_last_error(None)
+    assert L.lbm_study_propagate(0, 2, 64, 96, fake, ctypes.c_void_p(8192), None) == 1
+    assert L.lbm_study_collide(2, 8, 64, 96, 0.5, 0.0, fake, None) == 1
+    assert L.lbm_study_collide(2, 8, 64, 96, float("nan"), 0.0, fake, None) == 1
+    assert L.lbm_study_collide(2, 8, 64, 96, 0.7, float("inf"), fake, None) == 1
+    assert L.lbm_study_pack(3, 8, 64, 96, None, fake, None) == 1
+    assert L.lbm_study_unpack(7, 8, 64, 96, fake, fake, None) == 1
+    # a thin lattice whose propagate would need more than one grid's workgroups
+    assert L.lbm_study_propagate(1, 1, (1 << 26) // 7, 7, fake, ctypes.c_void_p(8192), None) == 2
+    with pytest.raises(ValueError):
+        lbm.study_bytes("aosoa", 1, 64, 96)
