@@ -479,6 +479,51 @@ def layout_study(lx=2160, ly=8192, reps=20):
     return out
 
 
+def hetero_study(lx=2048, ly=4096, steps=20):
+    """Host + GPU co-execution (section 5) on the 2048x4096 RT lattice, FP64:
+    the performance model's auto-tuned parameters (section 6) and predicted
+    optimum, then the measured rate for a sweep of m (border columns per
+    side on the host) beside the model's prediction."""
+    import torch
+
+    from paper_1703_04594_amd import inputs
+    from paper_1703_04594_amd.hetero import autotune
+    from paper_1703_04594_amd.lbm import Hetero, Lattice
+
+    threads = min(16, os.cpu_count() or 1)
+    dev = "cuda:0"
+    lat = Lattice(lx, ly, 0.7, -1e-5, 4 / 3, 2 / 3, step="fused", device=dev)
+    lat.init_rt(torch.tensor(inputs.rt_perturbation(lx, ly, 1), device=dev))
+    f0 = lat.get_pops().cpu().numpy()
+    del lat
+    torch.cuda.empty_cache()
+
+    def make(m):
+        h = Hetero(lx, ly, 0.7, -1e-5, 4 / 3, 2 / 3, m=m, host_threads=threads, device=dev)
+        h.set_pops(f0)
+        return h
+
+    model = autotune(make, lx, ly, m_probe=32, steps=steps)
+    log(f"bench: hetero model tau_d={model.tau_d:.3e} tau_h={model.tau_h:.3e} t_swap={model.t_swap:.3e}")
+    sweep = []
+    for m in (0, 2, 4, 8, 16, 32, 64, 128):
+        h = make(m)
+        h.step(3)
+        h.step(steps)
+        t = h.times()
+        h.close()
+        row = {"m": m, "host_fraction": round(2 * m / lx, 4),
+               "mlups": round(lx * ly / t["wall"] / 1e6, 1),
+               "model_mlups": round(model.mlups(lx, ly, m), 1),
+               "ms": {k: round(v * 1e3, 4) for k, v in t.items()}}
+        sweep.append(row)
+        log(f"bench: hetero {row}")
+    return {"lattice": f"{lx}x{ly}", "precision": "fp64", "host_threads": threads, "steps": steps,
+            "tau_d_ns_per_site": round(model.tau_d * 1e9, 5), "tau_h_ns_per_site": round(model.tau_h * 1e9, 4),
+            "t_swap_ms": round(model.t_swap * 1e3, 4), "m_balance": round(model.m_balance(lx), 2),
+            "best_m": model.best_m(lx, ly), "sweep": sweep}
+
+
 def profile_workload(args):
     """Short fixed sequence for rocprofv3 runs: a plain device copy of known
     size (calibrates the HBM byte counters), the reference copy of one
@@ -538,6 +583,8 @@ def main():
                     help="skip the FP32 accuracy and adjoint-at-scale measurements")
     ap.add_argument("--profile", action="store_true",
                     help="run the short fixed kernel sequence used under rocprofv3")
+    ap.add_argument("--hetero", action="store_true",
+                    help="host + GPU co-execution on the 2048x4096 lattice: model and m sweep (one JSON line)")
     ap.add_argument("--layout-study", action="store_true",
                     help="per-kernel FP64 times on the 2160x8192 lattice for each layout (one JSON line)")
     args = ap.parse_args()
@@ -547,6 +594,9 @@ def main():
         sys.exit(2)
     if args.profile:
         profile_workload(args)
+        return
+    if args.hetero:
+        print(json.dumps({"hetero": hetero_study()}), flush=True)
         return
     if args.layout_study:
         print(json.dumps({"layout_study": layout_study()}), flush=True)

@@ -242,6 +242,56 @@ lbm_status lbm_study_propagate(int layout, int vl, int lx, int ly, const double*
 lbm_status lbm_study_collide(int layout, int vl, int lx, int ly, double tau, double g_y, double* buf,
                              void* hip_stream);
 
+/* ---- host cores, and host + GPU co-execution -------------------------------- */
+/* Section 5 splits the lattice along x: m border columns on each side run on
+ * the host's cores, the remaining lx - 2m columns on the accelerator, and the
+ * two exchange three-column halos after every step.  Section 6 models the
+ * time per step as max(T_acc, T_host) + T_swap with T_acc = (lx - 2m) ly tau_d
+ * and T_host = 2m ly tau_h (one process: no inter-process term), which
+ * is least where T_acc = T_host.  FP64 only; lattices are x-periodic, y as in
+ * params.ybc; params.xmode / step_kind / layout / adjoint are ignored. */
+
+/* One fused step (pull streaming, wall rule, collide) on host cores over a
+ * whole x-periodic lattice in host memory, stored in the library's FP64
+ * column layout (lbm_host_lattice_bytes per buffer; fill with lbm_host_pack).
+ * These serve as the host part's building block and to time tau_h. */
+size_t lbm_host_lattice_bytes(const lbm_params* p);               /* 0 if invalid */
+/* canonical FP64 [37][lx][ly] (host) -> a buffer, and back; pack writes the
+ * sites only (ghost rows and halo columns keep their contents). */
+lbm_status lbm_host_pack(const lbm_params* p, const double* canon, double* buf);
+lbm_status lbm_host_unpack(const lbm_params* p, const double* buf, double* canon);
+/* n steps on nthreads host threads, alternating a -> b -> a ...: the state
+ * after n steps is in a if n is even, else in b.  In y-periodic mode the
+ * ghost rows of the source buffer are refreshed in place. */
+lbm_status lbm_host_step(const lbm_params* p, double* a, double* b, int64_t n, int nthreads);
+
+typedef struct lbm_hetero lbm_hetero;
+/* Device workspace bytes of the GPU part for m border columns per side
+ * (m = 0: the whole lattice on the GPU; else m >= 2 and lx - 2m >= 3);
+ * 0 if invalid. */
+size_t lbm_hetero_workspace_bytes(const lbm_params* p, int m);
+/* Creates a co-executed lattice: the GPU part in the caller's device
+ * workspace (256-byte aligned, lbm_hetero_workspace_bytes) on hip_stream, the
+ * host part (2 m + 6 columns, two buffers) in pinned host memory the library
+ * allocates, stepped by host_threads threads.  Errors as lbm_create. */
+lbm_status lbm_hetero_create(const lbm_params* p, int m, int host_threads, void* dev_workspace, size_t bytes,
+                             void* hip_stream, lbm_hetero** out);
+void lbm_hetero_destroy(lbm_hetero* h);
+/* Whole-lattice state as canonical FP64 [37][lx][ly] in host memory
+ * (synchronous; allocates a temporary device copy of the GPU part). */
+lbm_status lbm_hetero_set_pops(lbm_hetero* h, const double* host_canon);
+lbm_status lbm_hetero_get_pops(lbm_hetero* h, double* host_canon);
+/* n steps: per step, the GPU part's step is enqueued, the host part steps
+ * meanwhile, then the halos are copied both ways on the stream and the
+ * stream is synchronised.  Results equal lbm_step on the whole lattice up to
+ * rounding order (the host part is compiled separately). */
+lbm_status lbm_hetero_step(lbm_hetero* h, int64_t n);
+/* Per-step averages over the last lbm_hetero_step call, seconds:
+ * out = {wall time, host step, GPU step (HIP events), halo swap (events)}. */
+lbm_status lbm_hetero_times(const lbm_hetero* h, double out[4]);
+/* Message of the last error ("" if none); NULL: of lbm_hetero_create. */
+const char* lbm_hetero_last_error(const lbm_hetero* h);
+
 /* ---- misc ------------------------------------------------------------------ */
 
 /* Waits for the context's stream; LBM_ERR_HIP if queued work failed. */

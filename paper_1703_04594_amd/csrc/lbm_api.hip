@@ -629,3 +629,4 @@ double lbm_scale_c(void) { return C; }
 
 #include "lbm_adjoint_api.inc"
 #include "lbm_layouts_api.inc"
+#include "lbm_hetero_api.inc"

@@ -105,6 +105,25 @@ def lib() -> ctypes.CDLL:
     L.lbm_weights.restype = None
     L.lbm_scale_c.restype = ctypes.c_double
     ci = ctypes.c_int
+    L.lbm_host_lattice_bytes.argtypes = [PP]
+    L.lbm_host_lattice_bytes.restype = ctypes.c_size_t
+    L.lbm_host_pack.argtypes = [PP, vp, vp]
+    L.lbm_host_unpack.argtypes = [PP, vp, vp]
+    L.lbm_host_step.argtypes = [PP, vp, vp, i64, ci]
+    L.lbm_hetero_workspace_bytes.argtypes = [PP, ci]
+    L.lbm_hetero_workspace_bytes.restype = ctypes.c_size_t
+    L.lbm_hetero_create.argtypes = [PP, ci, ci, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
+    L.lbm_hetero_destroy.argtypes = [vp]
+    L.lbm_hetero_destroy.restype = None
+    L.lbm_hetero_set_pops.argtypes = [vp, vp]
+    L.lbm_hetero_get_pops.argtypes = [vp, vp]
+    L.lbm_hetero_step.argtypes = [vp, i64]
+    L.lbm_hetero_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+    L.lbm_hetero_last_error.argtypes = [vp]
+    L.lbm_hetero_last_error.restype = ctypes.c_char_p
+    for n in ("lbm_host_pack", "lbm_host_unpack", "lbm_host_step", "lbm_hetero_create", "lbm_hetero_set_pops",
+              "lbm_hetero_get_pops", "lbm_hetero_step", "lbm_hetero_times"):
+        getattr(L, n).restype = st
     L.lbm_study_bytes.argtypes = [ci, ci, ci, ci]
     L.lbm_study_bytes.restype = ctypes.c_size_t
     for n in ("lbm_study_pack", "lbm_study_unpack", "lbm_study_propagate"):
@@ -372,3 +391,122 @@ def study_collide(layout: str, vl: int, lx: int, ly: int, tau: float, g_y: float
     _ptr(buf, torch.float64, (NPOP * lx * ly,), buf.device)
     _study_check(lib().lbm_study_collide(*a, float(tau), float(g_y), ctypes.c_void_p(buf.data_ptr()),
                                          _stream(buf)), "study_collide")
+
+
+# ---------------------------------------------------------------------------
+# Host cores, and host + GPU co-execution (sections 5 and 6).  FP64 only.
+# ---------------------------------------------------------------------------
+import numpy as _np  # noqa: E402
+
+
+def _host_canon(a, lx, ly) -> _np.ndarray:
+    a = _np.ascontiguousarray(a, dtype=_np.float64)
+    if a.shape != (NPOP, lx, ly):
+        raise ValueError(f"expected a ({NPOP}, {lx}, {ly}) array, got {a.shape}")
+    return a
+
+
+def _dp(a: _np.ndarray) -> ctypes.c_void_p:
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def _aligned_zeros(n: int, align: int = 64) -> _np.ndarray:
+    """n float64 zeros starting on an `align`-byte boundary (whole cache
+    lines per block of 8 rows, so the host step can stream its stores)."""
+    raw = _np.zeros(n + align // 8)
+    off = (-raw.ctypes.data % align) // 8
+    return raw[off:off + n]
+
+
+class HostLattice:
+    """A whole x-periodic lattice stepped on host cores (the host part's
+    kernel), in host memory."""
+
+    def __init__(self, lx, ly, tau, g_y=0.0, t_bottom=1.0, t_top=1.0, ybc="walls", threads=1):
+        self.L = lib()
+        self.p = make_params(lx, ly, tau, g_y, t_bottom, t_top, "fp64", ybc)
+        n = int(self.L.lbm_host_lattice_bytes(ctypes.byref(self.p)))
+        if n == 0:
+            raise LBMError("invalid lattice parameters")
+        self.lx, self.ly, self.threads = lx, ly, int(threads)
+        self.buf = [_aligned_zeros(n // 8), _aligned_zeros(n // 8)]
+        self.cur = 0
+
+    def _check(self, st, what):
+        if st != 0:
+            raise LBMError(f"{what}: {self.L.lbm_last_error(None).decode()} (status {st})")
+
+    def set_pops(self, canon):
+        c = _host_canon(canon, self.lx, self.ly)
+        self._check(self.L.lbm_host_pack(ctypes.byref(self.p), _dp(c), _dp(self.buf[self.cur])), "host_pack")
+
+    def get_pops(self) -> _np.ndarray:
+        out = _np.empty((NPOP, self.lx, self.ly))
+        self._check(self.L.lbm_host_unpack(ctypes.byref(self.p), _dp(self.buf[self.cur]), _dp(out)), "host_unpack")
+        return out
+
+    def step(self, n: int = 1):
+        a, b = self.buf[self.cur], self.buf[1 - self.cur]
+        self._check(self.L.lbm_host_step(ctypes.byref(self.p), _dp(a), _dp(b), int(n), self.threads), "host_step")
+        if n % 2:
+            self.cur = 1 - self.cur
+
+
+class Hetero:
+    """A lattice split between host cores (m border columns on each side)
+    and the GPU (the rest), halos swapped every step."""
+
+    def __init__(self, lx, ly, tau, g_y=0.0, t_bottom=1.0, t_top=1.0, ybc="walls", m=0, host_threads=1,
+                 device="cuda"):
+        self.L = lib()
+        self.p = make_params(lx, ly, tau, g_y, t_bottom, t_top, "fp64", ybc)
+        self.lx, self.ly, self.m = lx, ly, int(m)
+        self.device = torch.device(device)
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        nbytes = int(self.L.lbm_hetero_workspace_bytes(ctypes.byref(self.p), self.m))
+        if nbytes == 0:
+            raise LBMError("invalid lattice parameters or split")
+        with torch.cuda.device(self.device):
+            self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            self.stream = torch.cuda.current_stream(self.device)
+        ws = (self.workspace.data_ptr() + 255) // 256 * 256
+        h = ctypes.c_void_p()
+        st = self.L.lbm_hetero_create(ctypes.byref(self.p), self.m, int(host_threads), ctypes.c_void_p(ws), nbytes,
+                                      ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        if st != 0:
+            raise LBMError(f"lbm_hetero_create: {self.L.lbm_hetero_last_error(None).decode()} (status {st})")
+        self.h = h
+
+    def _check(self, st, what):
+        if st != 0:
+            raise LBMError(f"{what}: {self.L.lbm_hetero_last_error(self.h).decode()} (status {st})")
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.lbm_hetero_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_pops(self, canon):
+        c = _host_canon(canon, self.lx, self.ly)
+        self._check(self.L.lbm_hetero_set_pops(self.h, _dp(c)), "hetero_set_pops")
+
+    def get_pops(self) -> _np.ndarray:
+        out = _np.empty((NPOP, self.lx, self.ly))
+        self._check(self.L.lbm_hetero_get_pops(self.h, _dp(out)), "hetero_get_pops")
+        return out
+
+    def step(self, n: int = 1):
+        self._check(self.L.lbm_hetero_step(self.h, int(n)), "hetero_step")
+
+    def times(self) -> dict:
+        """Per-step averages of the last step() call, seconds."""
+        t = (ctypes.c_double * 4)()
+        self._check(self.L.lbm_hetero_times(self.h, t), "hetero_times")
+        return {"wall": t[0], "host": t[1], "gpu": t[2], "swap": t[3]}

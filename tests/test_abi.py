@@ -23,7 +23,7 @@ def declared_functions():
 def test_every_declared_symbol_is_exported():
     L = lbm.lib()
     names = declared_functions()
-    assert len(names) == 34
+    assert len(names) == 46
     missing = [n for n in names if not hasattr(L, n)]
     assert not missing, missing
 

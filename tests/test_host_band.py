@@ -1,0 +1,75 @@
+"""The host-core step (the host part of host + GPU co-execution, section 5)
+against the CPU oracle, and the co-execution entry points' host-side
+validation.  CPU only: nothing here reaches a GPU.
+
+Bar: per population relative to its weight, max |f_host - f_ref| / w_l <=
+1e-12 after a few steps (FP64 on both sides, different rounding order)."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1703_04594_amd import inputs, lbm
+
+from _util import TAU, TB, TT, WC
+
+
+def relw(a, b):
+    return float(np.max(np.abs(a - b) / WC))
+
+
+def random_state(lx, ly, seed, amp=0.05):
+    return WC * (1.0 + amp * inputs.population_noise(lx, ly, seed))
+
+
+@pytest.mark.parametrize("ybc", ["walls", "periodic"])
+@pytest.mark.parametrize("lx,ly", [(13, 37), (9, 64)])
+def test_host_step_matches_oracle(ybc, lx, ly):
+    g = -1e-3
+    f0 = random_state(lx, ly, 11)
+    host = lbm.HostLattice(lx, ly, TAU, g, TB, TT, ybc=ybc, threads=2)
+    host.set_pops(f0)
+    assert np.array_equal(host.get_pops(), f0)
+    ref = oracle.RefLattice(lx, ly, TAU, g, TB, TT, ybc=oracle.WALL if ybc == "walls" else oracle.PERIODIC)
+    ref.set_pops(f0)
+    for n in (1, 2, 2):          # after 1, 3 and 5 steps
+        host.step(n)
+        ref.step(n)
+        err = relw(host.get_pops(), ref.get_pops())
+        assert err <= 1e-12, (ybc, lx, ly, err)
+
+
+def test_host_step_is_independent_of_the_thread_count():
+    lx, ly = 16, 45
+    f0 = random_state(lx, ly, 12)
+    outs = []
+    for threads in (1, 3, 8):
+        host = lbm.HostLattice(lx, ly, TAU, -1e-5, TB, TT, threads=threads)
+        host.set_pops(f0)
+        host.step(4)
+        outs.append(host.get_pops())
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+
+
+def test_co_execution_arguments_are_validated_on_the_host():
+    L = lbm.lib()
+    p = lbm.make_params(64, 48, TAU)
+    w0 = L.lbm_hetero_workspace_bytes(ctypes.byref(p), 0)
+    assert w0 == lbm.workspace_bytes(lbm.make_params(64, 48, TAU, step="fused"))
+    # m columns per side on the host: the GPU part is 64 - 2m + 6 columns wide
+    assert L.lbm_hetero_workspace_bytes(ctypes.byref(p), 8) == \
+        lbm.workspace_bytes(lbm.make_params(54, 48, TAU, step="fused"))
+    for m in (1, -1, 31, 32):    # m >= 2 and lx - 2m >= 3
+        assert L.lbm_hetero_workspace_bytes(ctypes.byref(p), m) == 0, m
+    p32 = lbm.make_params(64, 48, TAU, precision="fp32")
+    assert L.lbm_hetero_workspace_bytes(ctypes.byref(p32), 8) == 0
+    assert L.lbm_host_lattice_bytes(ctypes.byref(p32)) == 0
+    h = ctypes.c_void_p()
+    assert L.lbm_hetero_create(ctypes.byref(p), 1, 4, ctypes.c_void_p(4096), 1 << 30, None, ctypes.byref(h)) == 1
+    assert b"m must be" in L.lbm_hetero_last_error(None)
+    assert L.lbm_hetero_create(ctypes.byref(p), 8, 0, ctypes.c_void_p(4096), 1 << 30, None, ctypes.byref(h)) == 1
+    assert not h.value
+    buf = np.zeros(8)
+    assert L.lbm_host_step(ctypes.byref(p), buf.ctypes.data, buf.ctypes.data, 1, 1) == 1
+    assert L.lbm_host_step(ctypes.byref(p), buf.ctypes.data, None, 1, 1) == 1
