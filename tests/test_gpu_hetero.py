@@ -27,10 +27,10 @@ def random_state(lx, ly, seed, amp=0.05):
 
 
 @pytest.mark.parametrize("ybc", ["walls", "periodic"])
-@pytest.mark.parametrize("m", [0, 2, 5, 17])
-def test_split_lattice_matches_oracle(ybc, m):
-    lx, ly, g = 40, 30, -1e-3        # m = 17: the GPU keeps 6 columns
-    say(f"hetero {ybc} m={m}")
+@pytest.mark.parametrize("lx,m", [(40, 0), (40, 2), (40, 5), (40, 17), (41, 19)])
+def test_split_lattice_matches_oracle(ybc, lx, m):
+    ly, g = 30, -1e-3                 # (41, 19): the GPU keeps 3 columns, the least allowed
+    say(f"hetero {ybc} lx={lx} m={m}")
     f0 = random_state(lx, ly, 21)
     h = Hetero(lx, ly, TAU, g, TB, TT, ybc=ybc, m=m, host_threads=4, device=DEV)
     h.set_pops(f0)
