@@ -28,8 +28,6 @@ constexpr int PF = 32;  // prefetch distance, rows
 // B doubles: two AVX2 registers (one AVX-512 register where available)
 typedef double vb __attribute__((vector_size(B * sizeof(double))));
 
-constexpr int r2(int l) { return EX[l] * EX[l] + EY[l] * EY[l]; }
-
 // Compile-time loop: f(std::integral_constant<int, i>) for i = 0 .. N-1, so
 // that hop-table lookups inside are constants.
 template <class F, int... I>
@@ -37,15 +35,30 @@ inline void static_for_(F& f, std::integer_sequence<int, I...>) { (f(std::integr
 template <int N, class F>
 inline void static_for(F&& f) { static_for_(f, std::make_integer_sequence<int, N>{}); }
 
-// Shell constants of the Hermite coefficients (x2 = c^2 |e|^2):
+// |xi_l|^2 as the moments define it: xi_l = c e_l rounded per component, then
+// squared and summed (the GPU step's FP64 constants; constant-evaluated, so
+// every operation rounds once).
+constexpr double xi2_of_pop(int l)
+{
+    const double xx = C * EX[l], yy = C * EY[l];
+    return xx * xx + yy * yy;
+}
+constexpr double xi2_of_shell(int s)
+{
+    for (int l = 0; l < NPOP; ++l)
+        if (SHELL[l] == s) return xi2_of_pop(l);
+    return 0.0;
+}
+
+// Shell constants of the Hermite coefficients (x2 = |xi|^2 of the shell):
 //   A0 - 1 = u2 (-1/2 + u2/8) + th (k1 + u2 k2 + th k3),  A1 = 1 - u2/2 + th k4,
 //   A2 = 1/2 - u2/4 + th k5.
 struct ShellC { double k1, k2, k3, k4, k5; };
 constexpr ShellC shell_c(int s)
 {
-    return ShellC{(C2 * SHELL_R2[s] - 2.0) / 2.0, (4.0 - C2 * SHELL_R2[s]) / 4.0,
-                  (C2 * SHELL_R2[s] * C2 * SHELL_R2[s] - 8.0 * C2 * SHELL_R2[s] + 8.0) / 8.0,
-                  (C2 * SHELL_R2[s] - 4.0) / 2.0, (C2 * SHELL_R2[s] - 6.0) / 4.0};
+    const double x2 = xi2_of_shell(s);
+    return ShellC{(x2 - 2.0) / 2.0, (4.0 - x2) / 4.0, (x2 * x2 - 8.0 * x2 + 8.0) / 8.0, (x2 - 4.0) / 2.0,
+                  (x2 - 6.0) / 4.0};
 }
 
 inline int wrap(int x, int lx) { return x < 0 ? x + lx : (x >= lx ? x - lx : x); }
@@ -53,19 +66,22 @@ inline int wrap(int x, int lx) { return x < 0 ? x + lx : (x >= lx ? x - lx : x);
 // BGK collision of B sites in place.
 inline void collide_block(vb (&f)[NPOP], const BandArgs& a)
 {
-    vb m0 = {}, sx = {}, sy = {}, s2 = {};
+    vb m0 = {}, sx = {}, sy = {}, e2 = {};
     static_for<NPOP>([&](auto lc) {
         constexpr int l = decltype(lc)::value;
         m0 += f[l];
         if constexpr (EX[l] != 0) sx += double(EX[l]) * f[l];
         if constexpr (EY[l] != 0) sy += double(EY[l]) * f[l];
-        if constexpr (r2(l) != 0) s2 += double(r2(l)) * f[l];
+        if constexpr (l != 0) {
+            constexpr double x2 = xi2_of_pop(l);
+            e2 += x2 * f[l];
+        }
     });
     const vb rho = m0;
     const vb inv = 1.0 / rho;
     const vb ux = C * sx * inv;
     const vb uy0 = C * sy * inv;
-    const vb th = (C2 * s2 * inv - (ux * ux + uy0 * uy0)) * 0.5 - 1.0 + a.grav_th;
+    const vb th = (e2 * inv - (ux * ux + uy0 * uy0)) * 0.5 - 1.0 + a.grav_th;
     const vb uy = uy0 + a.tau_g;
     const vb u2 = ux * ux + uy * uy;
     const vb cux = C * ux, cuy = C * uy;

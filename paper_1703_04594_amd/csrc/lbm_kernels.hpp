@@ -389,7 +389,7 @@ __device__ __forceinline__ void site_macros(const S* p, long long plane, double&
         rho = m0;
         ux = C * sx / rho;
         uy = C * sy / rho;
-        T = 0.5 * (C2 * s2 / rho - (ux * ux + uy * uy));
+        T = 0.5 * (xi2_moment(f) / rho - (ux * ux + uy * uy));
     }
 }
 
@@ -469,7 +469,7 @@ __global__ __launch_bounds__(256) void k_conservation_partial(const S* __restric
         acc[0] += Store<S>::shifted ? 1.0 + m0 : m0;
         acc[1] += C * sx;
         acc[2] += C * sy;
-        acc[3] += Store<S>::shifted ? 2.0 + C2 * s2 : C2 * s2;
+        acc[3] += Store<S>::shifted ? 2.0 + C2 * s2 : xi2_moment(f);
     }
     block_sum_store<4, 256>(acc, partials + (size_t)blockIdx.x * 4);
 }

@@ -28,17 +28,79 @@ using namespace d2q37;
 
 constexpr int R2_OF(int l) { return EX[l] * EX[l] + EY[l] * EY[l]; }
 
-// Shell constants of the Hermite coefficients, evaluated at compile time.
-template <typename C> struct ShellK {
-    static constexpr C x2(int s) { return C(SHELL_R2[s]) * C(C2); }
-    static constexpr C k1(int s) { return (C(C2) * C(SHELL_R2[s]) - C(2)) / C(2); }
-    static constexpr C k2(int s) { return (C(4) - C(C2) * C(SHELL_R2[s])) / C(4); }
-    static constexpr C k3(int s) {
-        return (C(C2) * C(SHELL_R2[s]) * C(C2) * C(SHELL_R2[s]) - C(8) * C(C2) * C(SHELL_R2[s]) + C(8)) / C(8);
-    }
-    static constexpr C k4(int s) { return (C(C2) * C(SHELL_R2[s]) - C(4)) / C(2); }
-    static constexpr C k5(int s) { return (C(C2) * C(SHELL_R2[s]) - C(6)) / C(4); }
+// |xi_l|^2 in FP64 as the moments define it: the hop xi_l = c e_l rounded per
+// component, then squared and summed.  The FP64 step takes the equilibrium's
+// shell constants and the temperature's second moment from these values.
+// With c^2 |e|^2 rounded once instead (a different rounding of the same
+// constant), the FP64 temperature is biased by ~1e-16 relative at every
+// step; energy is conserved, so the bias accumulates, and the state drifts
+// from one computed with the per-component rounding by ~1.5e-15 per step.
+// Both arrays are constant-evaluated, so every operation rounds once.
+constexpr double xi2_of_pop(int l)
+{
+    const double xx = C * EX[l], yy = C * EY[l];
+    return xx * xx + yy * yy;
+}
+constexpr double xi2_of_shell(int s)
+{
+    for (int l = 0; l < NPOP; ++l)
+        if (SHELL[l] == s) return xi2_of_pop(l);
+    return 0.0;
+}
+struct Xi2Tables {
+    double pop[NPOP];
+    double shell[NSHELL];
+    double k1[NSHELL], k2[NSHELL], k3[NSHELL], k4[NSHELL], k5[NSHELL];
 };
+constexpr Xi2Tables make_xi2_tables()
+{
+    Xi2Tables t{};
+    for (int l = 0; l < NPOP; ++l) t.pop[l] = xi2_of_pop(l);
+    for (int s = 0; s < NSHELL; ++s) {
+        const double x2 = xi2_of_shell(s);
+        t.shell[s] = x2;
+        t.k1[s] = (x2 - 2.0) / 2.0;
+        t.k2[s] = (4.0 - x2) / 4.0;
+        t.k3[s] = (x2 * x2 - 8.0 * x2 + 8.0) / 8.0;
+        t.k4[s] = (x2 - 4.0) / 2.0;
+        t.k5[s] = (x2 - 6.0) / 4.0;
+    }
+    return t;
+}
+constexpr Xi2Tables XI2 = make_xi2_tables();
+
+// Shell constants of the Hermite coefficients, evaluated at compile time:
+// FP64 from the tables above, FP32 from c^2 |e|^2 in FP32.
+template <typename C> struct ShellK;
+template <> struct ShellK<double> {
+    static constexpr double x2(int s) { return XI2.shell[s]; }
+    static constexpr double k1(int s) { return XI2.k1[s]; }
+    static constexpr double k2(int s) { return XI2.k2[s]; }
+    static constexpr double k3(int s) { return XI2.k3[s]; }
+    static constexpr double k4(int s) { return XI2.k4[s]; }
+    static constexpr double k5(int s) { return XI2.k5[s]; }
+};
+template <> struct ShellK<float> {
+    using F = float;
+    static constexpr F x2(int s) { return F(SHELL_R2[s]) * F(C2); }
+    static constexpr F k1(int s) { return (F(C2) * F(SHELL_R2[s]) - F(2)) / F(2); }
+    static constexpr F k2(int s) { return (F(4) - F(C2) * F(SHELL_R2[s])) / F(4); }
+    static constexpr F k3(int s) {
+        return (F(C2) * F(SHELL_R2[s]) * F(C2) * F(SHELL_R2[s]) - F(8) * F(C2) * F(SHELL_R2[s]) + F(8)) / F(8);
+    }
+    static constexpr F k4(int s) { return (F(C2) * F(SHELL_R2[s]) - F(4)) / F(2); }
+    static constexpr F k5(int s) { return (F(C2) * F(SHELL_R2[s]) - F(6)) / F(4); }
+};
+
+// FP64 second moment sum_l |xi_l|^2 f_l with the per-population |xi_l|^2.
+template <typename V>
+__device__ __forceinline__ double xi2_moment(const V (&f)[NPOP])
+{
+    double e = 0.0;
+#pragma unroll
+    for (int l = 1; l < NPOP; ++l) e += XI2.pop[l] * (double)f[l];
+    return e;
+}
 
 template <typename C> __device__ __host__ constexpr C wshell(int s);
 template <> __device__ __host__ constexpr double wshell<double>(int s) { return W_SHELL[s]; }
@@ -149,7 +211,8 @@ __device__ __forceinline__ void collide_site(C (&f)[NPOP], const CollideArgs& ar
         // T - 1 = (sum (x2 - 2) d) / (2 rho) - u2 / 2
         th = (c2scale<C>() * s2 - C(2) * m0) * inv * C(0.5) - (ux * ux + uy0 * uy0) * C(0.5);
     } else {
-        th = (c2scale<C>() * s2 * inv - (ux * ux + uy0 * uy0)) * C(0.5) - C(1);
+        static_assert(sizeof(C) == 8, "the absolute form is FP64");
+        th = (xi2_moment(f) * inv - (ux * ux + uy0 * uy0)) * C(0.5) - C(1);
     }
     const C uy = uy0 + arg_taug<C>(args);
     th += arg_gth<C>(args);

@@ -346,10 +346,11 @@ def test_fp32_init_and_macros_are_fp64_exact_at_rest():
     assert torch.equal(rho, ones) and torch.equal(T, ones)
 
 
-def test_full_lattice_2048x4096_200_step_prefix():
-    """The 2048x4096 RT run at the benchmark's size and launch configuration:
-    every population of every site against the (OpenMP) oracle after 1, 10,
-    50, 100 and 200 steps, for the fused and the split step."""
+def test_full_lattice_2048x4096_1000_steps():
+    """The 2048x4096 RT run of the benchmark, at its size, launch
+    configuration and length: every population of every site against the
+    (OpenMP) oracle after 1, 10, 50, 100, 200, 400, 600, 800 and 1000 steps,
+    for the fused and the split step."""
     lx, ly = 2048, 4096
     say("full lattice 2048x4096: oracle init")
     ref, P = oracle_rt(lx, ly, 1, 0, openmp=True)
@@ -358,7 +359,7 @@ def test_full_lattice_2048x4096_200_step_prefix():
         lat.init_rt(tg(P))
     w = torch.tensor(W, dtype=torch.float64, device=DEV)[:, None]
     done = 0
-    for n in (1, 10, 50, 100, 200):
+    for n in (1, 10, 50, 100, 200, 400, 600, 800, 1000):
         ref.step(n - done)
         for lat in lats.values():
             lat.step(n - done)
