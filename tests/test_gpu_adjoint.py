@@ -8,11 +8,9 @@ point, FP64 arithmetic on both sides); whole rollouts to 1e-10; the
 directional derivatives of the 512x512 case agree with central differences
 to 1e-6 relative.
 """
-import numpy as np
 import pytest
 import torch
 
-import oracle
 from oracle.ref_torch import TorchD2Q37
 from paper_1703_04594_amd import inputs
 from paper_1703_04594_amd.autograd import RolloutConfig, rt_temperature

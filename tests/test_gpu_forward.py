@@ -12,9 +12,9 @@ import torch
 
 import oracle
 from paper_1703_04594_amd import inputs
-from paper_1703_04594_amd.lbm import Lattice, RtProfile
+from paper_1703_04594_amd.lbm import Lattice
 
-from _util import G, TAU, TB, TT, W, WC, oracle_rt, oracle_window_site, rt_fields, say
+from _util import G, TAU, TB, TT, W, WC, oracle_rt, oracle_window_site, say
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"

@@ -6,7 +6,6 @@ decays, exp(-nu k^2 t) with nu = T (tau - 1/2) / c^2 in lattice units, and
 that steady conduction between two walls gives a linear temperature profile.
 """
 import numpy as np
-import pytest
 
 import oracle
 
