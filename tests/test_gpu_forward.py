@@ -346,37 +346,6 @@ def test_fp32_init_and_macros_are_fp64_exact_at_rest():
     assert torch.equal(rho, ones) and torch.equal(T, ones)
 
 
-def test_full_lattice_2048x4096_1000_steps():
-    """The 2048x4096 RT run of the benchmark, at its size, launch
-    configuration and length: every population of every site against the
-    (OpenMP) oracle after 1, 10, 50, 100, 200, 400, 600, 800 and 1000 steps,
-    for the fused and the split step."""
-    lx, ly = 2048, 4096
-    say("full lattice 2048x4096: oracle init")
-    ref, P = oracle_rt(lx, ly, 1, 0, openmp=True)
-    lats = {k: Lattice(lx, ly, TAU, G, TB, TT, step=k, device=DEV) for k in ("fused", "split")}
-    for lat in lats.values():
-        lat.init_rt(tg(P))
-    w = torch.tensor(W, dtype=torch.float64, device=DEV)[:, None]
-    done = 0
-    for n in (1, 10, 50, 100, 200, 400, 600, 800, 1000):
-        ref.step(n - done)
-        for lat in lats.values():
-            lat.step(n - done)
-        done = n
-        want = ref.get_pops()
-        for k, lat in lats.items():
-            got = lat.get_pops()
-            err = 0.0
-            for l in range(37):
-                d = (got[l] - torch.from_numpy(want[l]).to(DEV)).abs().max() / w[l]
-                err = max(err, float(d))
-            say(f"  step {n} {k}: max |f - f_ref| / w = {err:.2e}")
-            assert err <= 1e-12, (n, k, err)
-            del got
-        del want
-
-
 @pytest.mark.parametrize("step", ["split", "fused"])
 def test_full_size_2048x4096_sampled_parity(step):
     """At the full 2048x4096 size and the benchmark's launch configuration:
