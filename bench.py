@@ -494,7 +494,7 @@ def layout_study(lx=2160, ly=8192, reps=20):
 
 
 def hetero_study(lx=2048, ly=4096, steps=20):
-    """Host + GPU co-execution (section 5) on the 2048x4096 RT lattice, FP64:
+    """Host + GPU co-execution (section 5) on an lx x ly RT lattice, FP64:
     the performance model's auto-tuned parameters (section 6) and predicted
     optimum, then the measured rate for a sweep of m (border columns per
     side on the host) beside the model's prediction."""
@@ -521,6 +521,8 @@ def hetero_study(lx=2048, ly=4096, steps=20):
     log(f"bench: hetero model tau_d={model.tau_d:.3e} tau_h={model.tau_h:.3e} t_swap={model.t_swap:.3e}")
     sweep = []
     for m in (0, 2, 4, 8, 16, 32, 64, 128):
+        if lx - 2 * m < 3:
+            continue
         h = make(m)
         h.step(3)
         h.step(steps)
@@ -598,7 +600,8 @@ def main():
     ap.add_argument("--profile", action="store_true",
                     help="run the short fixed kernel sequence used under rocprofv3")
     ap.add_argument("--hetero", action="store_true",
-                    help="host + GPU co-execution on the 2048x4096 lattice: model and m sweep (one JSON line)")
+                    help="host + GPU co-execution on 1024x2048, 2048x4096 and 2160x8192: model and m sweep "
+                         "(one JSON line)")
     ap.add_argument("--layout-study", action="store_true",
                     help="per-kernel FP64 times on the 2160x8192 lattice for each layout (one JSON line)")
     args = ap.parse_args()
@@ -610,7 +613,9 @@ def main():
         profile_workload(args)
         return
     if args.hetero:
-        print(json.dumps({"hetero": hetero_study()}), flush=True)
+        # three lattice sizes, as the paper's co-execution study uses
+        out = [hetero_study(lx, ly) for lx, ly in ((1024, 2048), (2048, 4096), (2160, 8192))]
+        print(json.dumps({"hetero": out}), flush=True)
         return
     if args.layout_study:
         print(json.dumps({"layout_study": layout_study()}), flush=True)
