@@ -282,12 +282,16 @@ void lbm_hetero_destroy(lbm_hetero* h);
 lbm_status lbm_hetero_set_pops(lbm_hetero* h, const double* host_canon);
 lbm_status lbm_hetero_get_pops(lbm_hetero* h, double* host_canon);
 /* n steps: per step, the GPU part's step is enqueued, the host part steps
- * meanwhile, then the halos are copied both ways on the stream and the
- * stream is synchronised.  Results equal lbm_step on the whole lattice up to
- * rounding order (the host part is compiled separately). */
+ * meanwhile, then the halos are exchanged: each side packs what the other's
+ * halo columns are read for (the populations that cross the seam, and the
+ * wall rows of the rest), one copy each way on the stream, unpack.  Results
+ * equal lbm_step on the whole lattice up to rounding order (the host part is
+ * compiled separately). */
 lbm_status lbm_hetero_step(lbm_hetero* h, int64_t n);
 /* Per-step averages over the last lbm_hetero_step call, seconds:
- * out = {wall time, host step, GPU step (HIP events), halo swap (events)}. */
+ * out = {wall time, host step, GPU step (HIP events), halo exchange (HIP
+ * events from the end of the GPU step through the GPU's unpack, plus the
+ * host's unpack)}. */
 lbm_status lbm_hetero_times(const lbm_hetero* h, double out[4]);
 /* Message of the last error ("" if none); NULL: of lbm_hetero_create. */
 const char* lbm_hetero_last_error(const lbm_hetero* h);

@@ -203,4 +203,23 @@ void fused_step(const double* src_c, double* dst, const BandGeo& g, const BandAr
     }
 }
 
+void seam_copy(double* buf, const BandGeo& g, const SeamList& s, double* stage, bool pack, int nthreads)
+{
+#pragma omp parallel for num_threads(nthreads) schedule(static)
+    for (int j = 0; j < s.nseg; ++j) {
+        double* seg = buf + g.origin - g.gr + (long long)s.seg_col[j] * g.cs + (long long)s.seg_pop[j] * g.ps;
+        double* st = stage + (size_t)j * g.ps;
+        if (pack) std::memcpy(st, seg, sizeof(double) * g.ps);
+        else std::memcpy(seg, st, sizeof(double) * g.ps);
+    }
+    double* st = stage + (size_t)s.nseg * g.ps;
+    for (int e = 0; e < s.nwall * 6; ++e) {
+        const int w = e / 6, r = e % 6;
+        const int y = r < 3 ? r : g.ly - 6 + r;
+        double* q = buf + g.origin + (long long)s.wall_col[w] * g.cs + (long long)s.wall_pop[w] * g.ps + y;
+        if (pack) st[e] = *q;
+        else *q = st[e];
+    }
+}
+
 }  // namespace lbm_host

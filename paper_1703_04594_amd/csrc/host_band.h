@@ -15,7 +15,27 @@ namespace lbm_host {
 struct BandGeo {
     int lx, ly;
     long long ps, cs, origin;
+    int gr;   // ghost rows above and below each segment
 };
+
+// One halo message between the two parts of a split lattice: whole padded
+// population segments (ps values each, in list order), then the six wall
+// rows (y = 0, 1, 2, ly-3, ly-2, ly-1) of further populations.  A halo
+// column needs only the populations whose hop reaches the receiver's own
+// columns from it, plus, for the wall rule's mirror densities, the wall rows
+// of the others.  Columns are those of the lattice that packs or unpacks.
+struct SeamList {
+    int nseg, nwall;
+    short seg_col[64];
+    unsigned char seg_pop[64];
+    short wall_col[256];
+    unsigned char wall_pop[256];
+};
+
+inline size_t seam_values(const SeamList& s, long long ps) { return (size_t)s.nseg * ps + (size_t)s.nwall * 6; }
+
+// pack: the listed data of buf -> stage; else stage -> buf.
+void seam_copy(double* buf, const BandGeo& g, const SeamList& s, double* stage, bool pack, int nthreads);
 
 struct BandArgs {
     double omega, tau_g, grav_th;   // 1/tau, tau g_y, tau (1 - tau) g_y^2 / 2
