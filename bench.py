@@ -294,6 +294,7 @@ def fp32_accuracy(args, nsteps=5000, every=500):
             row[name + "_vs_spread"] = d / float((x64 - x64.mean()).norm())
             row[name + "_vs_size"] = d / float(x64.norm())
         row["u"] = float((u32 - u64).norm()) / max(float(u64.norm()), floor_u)
+        row["u_norm"] = float(u64.norm())   # the denominator: a dip in |u| shows up as a spike in "u"
         rows.append({k2: (round(v, 9) if isinstance(v, float) else v) for k2, v in row.items()})
         log(f"bench: fp32 accuracy {row}")
     del lats
