@@ -42,8 +42,10 @@ def test_host_side_validation():
     n = lbm.workspace_bytes(good)
     assert n > 37 * 2 * 64 * 48 * 8
     for bad in (lbm.make_params(6, 48, 0.7), lbm.make_params(64, 6, 0.7), lbm.make_params(64, 48, 0.5),
-                lbm.make_params(64, 48, float("nan"))):
+                lbm.make_params(64, 48, float("nan")),
+                lbm.make_params(1 << 16, (1 << 15) + 1, 0.7)):      # more than 2^31 sites
         assert lbm.workspace_bytes(bad) == 0
+    assert lbm.workspace_bytes(lbm.make_params(1 << 16, 1 << 15, 0.7)) > 0      # exactly 2^31 sites
     p = lbm.make_params(64, 48, 0.7)
     p.precision = 7
     assert lbm.workspace_bytes(p) == 0

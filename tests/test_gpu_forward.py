@@ -193,6 +193,39 @@ def test_ragged_lattices(step, lx, ly, ybc):
     assert err <= 1e-12, (err)
 
 
+@pytest.mark.parametrize("tau", [0.505, 2.5])
+@pytest.mark.parametrize("step", ["split", "fused"])
+def test_relaxation_time_extremes_match_oracle(tau, step):
+    """Strong over-relaxation (omega = 1/tau near 2) and weak relaxation, with
+    walls and gravity: 20 steps against the oracle."""
+    lx, ly, g = 30, 41, -1e-4
+    say(f"tau {tau} {step}")
+    f0 = random_state(lx, ly, 9, amp=0.02)
+    lat = Lattice(lx, ly, tau, g, TB, TT, step=step, device=DEV)
+    lat.set_pops(tg(f0))
+    lat.step(20)
+    ref = oracle.RefLattice(lx, ly, tau, g, TB, TT)
+    ref.set_pops(f0)
+    ref.step(20)
+    err = relw(lat.get_pops().cpu().numpy(), ref.get_pops())
+    assert err <= 1e-12, (tau, step, err)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_zero_steps_change_nothing(precision):
+    lx, ly = 20, 24
+    say(f"zero steps {precision}")
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    f0 = random_state(lx, ly, 10, amp=0.02)
+    if precision == "fp32":
+        f0 = f0 - WC
+    lat = Lattice(lx, ly, TAU, G, TB, TT, precision=precision, step="fused", device=DEV)
+    lat.set_pops(tg(f0, dt))
+    before = lat.get_pops()
+    lat.step(0)
+    assert torch.equal(lat.get_pops(), before)
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("ybc,xmode", [("walls", "wrap"), ("periodic", "wrap"), ("walls", "halo")])
 def test_step_state_equals_step(precision, ybc, xmode):

@@ -66,7 +66,9 @@ def test_placement_and_round_trip(layout, vl):
 
 @pytest.mark.parametrize("layout,vl,lx,ly", [(lay, vl, 13, 96) for lay, vl in CASES]
                          + [("aos", 1, 37, 200), ("soa", 1, 37, 200), ("csoa", 8, 37, 200),
-                            ("caosoa", 8, 37, 200), ("csoa", 64, 9, 192), ("caosoa", 64, 9, 192)])
+                            ("caosoa", 8, 37, 200), ("csoa", 64, 9, 192), ("caosoa", 64, 9, 192),
+                            # the smallest lattices each layout takes
+                            ("aos", 1, 7, 7), ("soa", 1, 7, 7), ("csoa", 2, 7, 8), ("caosoa", 2, 7, 8)])
 def test_propagate_is_the_oracle_permutation(layout, vl, lx, ly):
     say(f"study propagate {layout} vl={vl} {lx}x{ly}")
     t = tagged(lx, ly)

@@ -40,6 +40,28 @@ def test_host_step_matches_oracle(ybc, lx, ly):
         assert err <= 1e-12, (ybc, lx, ly, err)
 
 
+@pytest.mark.parametrize("tau", [0.505, 2.5])
+def test_host_step_relaxation_extremes(tau):
+    lx, ly = 11, 29
+    f0 = random_state(lx, ly, 13, amp=0.02)
+    host = lbm.HostLattice(lx, ly, tau, -1e-4, TB, TT, threads=2)
+    host.set_pops(f0)
+    host.step(10)
+    ref = oracle.RefLattice(lx, ly, tau, -1e-4, TB, TT)
+    ref.set_pops(f0)
+    ref.step(10)
+    assert relw(host.get_pops(), ref.get_pops()) <= 1e-12
+
+
+def test_host_zero_steps_change_nothing():
+    lx, ly = 9, 16
+    f0 = random_state(lx, ly, 14)
+    host = lbm.HostLattice(lx, ly, TAU, 0.0, TB, TT)
+    host.set_pops(f0)
+    host.step(0)
+    assert np.array_equal(host.get_pops(), f0)
+
+
 def test_host_step_is_independent_of_the_thread_count():
     lx, ly = 16, 45
     f0 = random_state(lx, ly, 12)
