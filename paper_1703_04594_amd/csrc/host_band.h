@@ -26,9 +26,9 @@ struct BandGeo {
 // of the others.  Columns are those of the lattice that packs or unpacks.
 struct SeamList {
     int nseg, nwall;
-    short seg_col[64];
+    int seg_col[64];
     unsigned char seg_pop[64];
-    short wall_col[256];
+    int wall_col[256];
     unsigned char wall_pop[256];
 };
 

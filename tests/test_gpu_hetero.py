@@ -76,3 +76,25 @@ def test_split_2048x4096_rt():
             ref = oracle_window_site(P, lx, ly, x0, y0, n)
             e = float(np.max(np.abs(got[:, x0, y0] - ref) / WC[:, 0, 0]))
             assert e <= 1e-12, (x0, y0, e)
+
+
+def test_split_beyond_16_bit_columns():
+    """A lattice wider than 32767 columns: the halo messages name GPU
+    columns past the 16-bit range.  The whole lattice against the GPU-only
+    step after 3 steps."""
+    lx, ly, m, n = 40000, 12, 3, 3
+    say("hetero 40000x12 m=3")
+    f0 = random_state(lx, ly, 23)
+    lat = Lattice(lx, ly, TAU, -1e-3, TB, TT, step="fused", device=DEV)
+    lat.set_pops(torch.tensor(f0, device=DEV))
+    lat.step(n)
+    want = lat.get_pops().cpu().numpy()
+    del lat
+    torch.cuda.empty_cache()
+    h = Hetero(lx, ly, TAU, -1e-3, TB, TT, m=m, host_threads=4, device=DEV)
+    h.set_pops(f0)
+    h.step(n)
+    got = h.get_pops()
+    h.close()
+    err = relw(got, want)
+    assert err <= 1e-12, err
