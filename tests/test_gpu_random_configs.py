@@ -142,3 +142,95 @@ def test_random_split_lattice_matches_oracle(case):
     ref.step(c["n"])
     err = float(np.max(np.abs(got - ref.get_pops()) / WC))
     assert err <= 1e-12, (c, err)
+
+
+def draw_adjoint_cases(n, seed=20170316):
+    rng = np.random.default_rng(seed)
+    cases = []
+    for i in range(n):
+        precision = "fp32" if rng.random() < 0.3 else "fp64"
+        cases.append(dict(lx=int(rng.integers(7, 41)), ly=int(rng.integers(7, 41)),
+                          tau=float(rng.uniform(0.52, 2.0)), g=float(rng.uniform(-2e-3, 2e-3)),
+                          tb=float(rng.uniform(0.7, 1.5)), tt=float(rng.uniform(0.7, 1.5)),
+                          ybc=str(rng.choice(["walls", "periodic"])), layout=str(rng.choice(["columns", "planes"])),
+                          precision=precision, n=1 if precision == "fp32" else int(rng.integers(1, 4)),
+                          seed=700 + 2 * i))
+    return cases
+
+
+ADJOINT_CASES = draw_adjoint_cases(16)
+
+
+def dtau_term_scale(m, f0, tau, lam_n, n):
+    """Sum over steps k and sites of |sum_l lambda_{k+1,l} d step_l(f_k)/d tau|:
+    the magnitude of the terms whose sum is dL/dtau, so the scale its
+    rounding error is relative to (the sum itself can cancel by 100x)."""
+    tc = torch.tensor(tau, dtype=torch.float64)
+    states = [f0]
+    with torch.no_grad():
+        for _ in range(n):
+            states.append(m.step(states[-1], tc))
+    total = 0.0
+    for k in range(n):
+        if k + 1 == n:
+            lam = lam_n
+        else:
+            fk1 = states[k + 1].clone().requires_grad_(True)
+            out = fk1
+            for _ in range(k + 1, n):
+                out = m.step(out, tc)
+            lam = torch.autograd.grad((out * lam_n).sum(), fk1)[0]
+        t = torch.tensor(tau, dtype=torch.float64, requires_grad=True)
+        out = m.step(states[k], t)
+        v = torch.zeros_like(out, requires_grad=True)   # d/dtau of out, by the double-VJP identity
+        gt = torch.autograd.grad(out, t, v, create_graph=True)[0]
+        tangent = torch.autograd.grad(gt, v)[0]
+        total += float((lam * tangent).sum(0).abs().sum())
+    return total
+
+
+@pytest.mark.parametrize("case", ADJOINT_CASES, ids=[f"{i}" for i in range(len(ADJOINT_CASES))])
+def test_random_reverse_steps_match_autograd(case):
+    """n reverse steps (FP64 lambda) against autograd of the PyTorch-CPU
+    float64 restatement of the step: lambda_0 to 1e-12 relative to its
+    largest value, d/dtau to 1e-12 relative to the summed magnitude of its
+    per-site terms.  FP32 state: one step from the FP32-stored state, whose
+    FP64 value is the oracle's linearisation point."""
+    from oracle.ref_torch import TorchD2Q37
+    c = case
+    say(f"random adjoint case {c}")
+    lx, ly = c["lx"], c["ly"]
+    w = torch.tensor(WC)
+    noise = torch.tensor(inputs.population_noise(lx, ly, c["seed"]))
+    lam_n = torch.tensor(inputs.population_noise(lx, ly, c["seed"] + 1))
+    lat = Lattice(lx, ly, c["tau"], c["g"], c["tb"], c["tt"], precision=c["precision"], ybc=c["ybc"], adjoint=True,
+                  layout=c["layout"], device=DEV)
+    if c["precision"] == "fp64":
+        f_store = w * (1 + 0.05 * noise)
+        f64 = f_store.clone()
+    else:
+        f_store = (w * 0.05 * noise).to(torch.float32)
+        f64 = w + f_store.to(torch.float64)
+    lat.set_pops(f_store.to(DEV))
+    states = []
+    for _ in range(c["n"]):
+        states.append(lat.get_state())
+        lat.step(1)
+    lat.set_lambda(lam_n.to(DEV))
+    dacc = torch.zeros((), dtype=torch.float64, device=DEV)
+    for st in reversed(states):
+        lat.adjoint_step(st, dacc)
+    lam0 = lat.get_lambda().cpu()
+    dtau = float(dacc.cpu())
+    lat.close()
+
+    m = TorchD2Q37(lx, ly, c["g"], c["tb"], c["tt"], walls=(c["ybc"] == "walls"))
+    f = f64.clone().requires_grad_(True)
+    tau = torch.tensor(c["tau"], dtype=torch.float64, requires_grad=True)
+    out = f
+    for _ in range(c["n"]):
+        out = m.step(out, tau)
+    (out * lam_n).sum().backward()
+    e_lam = float((lam0 - f.grad).abs().max() / f.grad.abs().max())
+    e_tau = abs(dtau - float(tau.grad)) / dtau_term_scale(m, f64, c["tau"], lam_n, c["n"])
+    assert e_lam <= 1e-12 and e_tau <= 1e-12, (c, e_lam, e_tau)
