@@ -95,3 +95,28 @@ def test_co_execution_arguments_are_validated_on_the_host():
     buf = np.zeros(8)
     assert L.lbm_host_step(ctypes.byref(p), buf.ctypes.data, buf.ctypes.data, 1, 1) == 1
     assert L.lbm_host_step(ctypes.byref(p), buf.ctypes.data, None, 1, 1) == 1
+
+
+def draw_host_cases(n, seed=20170317):
+    rng = np.random.default_rng(seed)
+    return [dict(lx=int(rng.integers(7, 60)), ly=int(rng.integers(7, 140)), tau=float(rng.uniform(0.52, 2.0)),
+                 g=float(rng.uniform(-1e-3, 1e-3)), tb=float(rng.uniform(0.7, 1.5)), tt=float(rng.uniform(0.7, 1.5)),
+                 ybc=str(rng.choice(["walls", "periodic"])), threads=int(rng.integers(1, 5)),
+                 n=int(rng.integers(1, 6)), seed=900 + i) for i in range(n)]
+
+
+@pytest.mark.parametrize("case", draw_host_cases(24), ids=[str(i) for i in range(24)])
+def test_host_step_random_configuration(case):
+    """Seeded random shapes (ragged against the 8-row blocks), relaxation
+    times, gravity, wall temperatures, boundaries and thread counts."""
+    c = case
+    f0 = random_state(c["lx"], c["ly"], c["seed"], amp=0.02)
+    host = lbm.HostLattice(c["lx"], c["ly"], c["tau"], c["g"], c["tb"], c["tt"], ybc=c["ybc"], threads=c["threads"])
+    host.set_pops(f0)
+    host.step(c["n"])
+    ref = oracle.RefLattice(c["lx"], c["ly"], c["tau"], c["g"], c["tb"], c["tt"],
+                            ybc=oracle.WALL if c["ybc"] == "walls" else oracle.PERIODIC)
+    ref.set_pops(f0)
+    ref.step(c["n"])
+    err = relw(host.get_pops(), ref.get_pops())
+    assert err <= 1e-12, (c, err)
