@@ -607,6 +607,8 @@ def main():
     ap.add_argument("--hetero", action="store_true",
                     help="host + GPU co-execution on 1024x2048, 2048x4096 and 2160x8192: model and m sweep "
                          "(one JSON line)")
+    ap.add_argument("--hetero-size", default="1024x2048,2048x4096,2160x8192",
+                    help="lattices for --hetero, as LXxLY[,LXxLY...]")
     ap.add_argument("--layout-study", action="store_true",
                     help="per-kernel FP64 times on the 2160x8192 lattice for each layout (one JSON line)")
     args = ap.parse_args()
@@ -618,8 +620,9 @@ def main():
         profile_workload(args)
         return
     if args.hetero:
-        # three lattice sizes, as the paper's co-execution study uses
-        out = [hetero_study(lx, ly) for lx, ly in ((1024, 2048), (2048, 4096), (2160, 8192))]
+        # by default three lattice sizes, as the paper's co-execution study uses
+        sizes = [tuple(int(v) for v in s.split("x")) for s in args.hetero_size.split(",")]
+        out = [hetero_study(lx, ly) for lx, ly in sizes]
         print(json.dumps({"hetero": out}), flush=True)
         return
     if args.layout_study:
