@@ -309,11 +309,19 @@ __global__ __launch_bounds__(SITE_THREADS) void k_step_fused(const S* __restrict
     if (y >= g.ly) return;
     const unsigned yb = (unsigned)y * (unsigned)sizeof(S);
     Cc f[NPOP];
+    // FP64: the 37 gathers are issued at raised wave priority, so a wave that
+    // reaches them is not held behind other waves' collide arithmetic
+    // (measured 0.4% on the 2048x4096 step; results are unchanged).
+    if constexpr (sizeof(S) == 8) __builtin_amdgcn_s_setprio(3);
 #pragma unroll
     for (int l = 0; l < NPOP; ++l) {
         int xs = x - EX[l];
         if (WRAP) xs = wrap_x(xs, g.lx);
         f[l] = (Cc)ld_at(src + (size_t)l * g.ps + g.origin + (long long)xs * g.cs - EY[l], yb);
+    }
+    if constexpr (sizeof(S) == 8) {
+        __builtin_amdgcn_sched_barrier(0);
+        __builtin_amdgcn_s_setprio(0);
     }
     if (WALLS && (y < 3 || y >= g.ly - 3)) {
 #pragma unroll
