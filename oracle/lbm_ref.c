@@ -467,19 +467,27 @@ int ref_get_macros(const ref_lattice* L, double* rho, double* ux, double* uy, do
 }
 
 /* Lattice totals of the collision invariants: sum rho, sum j_x, sum j_y,
- * sum E with E = sum_l |xi_l|^2 f_l.  Serial, fixed order. */
+ * sum E with E = sum_l |xi_l|^2 f_l (eq. (2) summed over the lattice).
+ * Serial, fixed order, accumulated in quad precision: a double accumulator
+ * adding 10^5 values whose low-order bits all agree (FP32 deviations widened
+ * onto the fixed FP64 weights) rounds the same way at every addition, and
+ * its error grows like n ulp/2 (1e-8 of a 3000-site total), far above the
+ * error of the sums it is meant to check. */
 int ref_conservation(const ref_lattice* L, double out[4])
 {
-    double a = 0, b = 0, c = 0, d = 0;
+    __float128 a = 0, b = 0, c = 0, d = 0;
     for (int l = 0; l < Q; ++l) {
         double x2 = XI_X[l] * XI_X[l] + XI_Y[l] * XI_Y[l];
         for (int x = 0; x < L->lx; ++x)
             for (int y = 0; y < L->ly; ++y) {
                 double v = AT(L->cur, L, l, x, y);
-                a += v; b += XI_X[l] * v; c += XI_Y[l] * v; d += x2 * v;
+                a += v;
+                b += (__float128)XI_X[l] * v;
+                c += (__float128)XI_Y[l] * v;
+                d += (__float128)x2 * v;
             }
     }
-    out[0] = a; out[1] = b; out[2] = c; out[3] = d;
+    out[0] = (double)a; out[1] = (double)b; out[2] = (double)c; out[3] = (double)d;
     return 0;
 }
 
