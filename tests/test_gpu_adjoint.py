@@ -300,3 +300,26 @@ def test_lambda_round_trip_wider_than_grid_y(lam):
         lam1 = lam1.float().double()
     lat.set_lambda(lam1.to(DEV))
     assert torch.equal(lat.get_lambda().cpu(), lam1)
+
+
+def test_set_tau_applies_to_the_reverse_step():
+    """lbm_set_tau also sets the tau of later reverse steps: a context made
+    at tau = 0.7 and switched to 0.95 gives bitwise the reverse step (lambda_n
+    and the d/dtau term) of a context made at 0.95."""
+    lx, ly, g, t2 = 24, 20, -1e-3, 0.95
+    say("adjoint after set_tau")
+    noise = torch.tensor(inputs.population_noise(lx, ly, 71))
+    lam1 = torch.tensor(inputs.population_noise(lx, ly, 72))
+    f_store = (WT[:, None, None] * (1 + 0.05 * noise)).to(DEV)
+    out = []
+    for tau0 in (TAU, t2):
+        lat = Lattice(lx, ly, tau0, g, TB, TT, adjoint=True, device=DEV)
+        if tau0 != t2:
+            lat.set_tau(t2)
+        lat.set_pops(f_store)
+        st = lat.get_state()
+        lat.set_lambda(lam1.to(DEV))
+        dacc = torch.zeros((), dtype=torch.float64, device=DEV)
+        lat.adjoint_step(st, dacc)
+        out.append((lat.get_lambda(), dacc))
+    assert torch.equal(out[0][0], out[1][0]) and torch.equal(out[0][1], out[1][1])

@@ -396,3 +396,114 @@ def test_full_size_2048x4096_sampled_parity(step):
         err = float(np.max(np.abs(got - want) / W))
         say(f"  site ({x0},{y0}) err {err:.2e}")
         assert err <= 1e-12, (x0, y0, err)
+
+
+@pytest.mark.parametrize("ybc,xmode", [("walls", "wrap"), ("periodic", "wrap"), ("walls", "halo")])
+def test_fp32_conservation_matches_oracle_of_the_widened_state(ybc, xmode):
+    """lbm_conservation on FP32-shifted storage (the FP64 reduction the
+    shifted form keeps) after gravity steps: equal to the oracle's totals of
+    the same state widened to FP64 (f = w + d), up to summation order."""
+    lx, ly, g, n = 45, 67, -1e-3, 12
+    say(f"fp32 conservation {ybc} {xmode}")
+    d0 = (WC * 0.05 * inputs.population_noise(lx, ly, 51)).astype(np.float32)
+    lat = Lattice(lx, ly, TAU, g, TB, TT, precision="fp32", ybc=ybc, xmode=xmode, step="fused", device=DEV)
+    lat.set_pops(tg(d0, torch.float32))
+    lat.step(n)
+    got = lat.conservation().cpu().numpy()
+    f = WC + lat.get_pops().cpu().numpy().astype(np.float64)
+    ref = oracle.RefLattice(lx, ly, TAU, g, TB, TT, ybc=oracle.PERIODIC if ybc == "periodic" else oracle.WALL)
+    ref.set_pops(f)
+    want = ref.conservation()
+    ex, ey = oracle.velocity_table()
+    c = oracle.scale_c()
+    xx, yy = (c * ex)[:, None, None], (c * ey)[:, None, None]
+    mag = np.array([np.abs(f).sum(), np.abs(xx * f).sum(), np.abs(yy * f).sum(),
+                    ((xx * xx + yy * yy) * np.abs(f)).sum()])
+    say(f"  rel diff {np.abs(got - want) / mag}")
+    assert np.all(np.abs(got - want) <= 1e-12 * mag)
+
+
+def test_fp32_conservation_tracks_the_gravity_impulse():
+    """Periodic FP32 lattice with gravity: per step the totals move by the
+    closed forms of the collision (mass and x momentum kept, y momentum
+    + g M, E + 2 g J_y + g^2 M), up to the FP32 rounding of the stored
+    deviations (2^-24 of each, unbiased: ~1e-8 of the totals here)."""
+    lx, ly, g = 40, 48, -2e-3
+    say("fp32 conservation: gravity impulse")
+    d0 = (WC * 0.05 * inputs.population_noise(lx, ly, 52)).astype(np.float32)
+    lat = Lattice(lx, ly, TAU, g, ybc="periodic", precision="fp32", step="fused", device=DEV)
+    lat.set_pops(tg(d0, torch.float32))
+    for _ in range(5):
+        M, Jx, Jy, E = lat.conservation().cpu().numpy()
+        lat.step(1)
+        got = lat.conservation().cpu().numpy()
+        want = np.array([M, Jx, Jy + g * M, E + 2 * g * Jy + g * g * M])
+        err = np.abs(got - want) / np.array([M, M, M, E])
+        say(f"  impulse error {err}")
+        assert np.all(err <= 1e-6), err
+        assert abs(got[2] - Jy) > 1e-4 * M
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_init_with_velocity_matches_oracle(precision):
+    """lbm_init at |u| up to 0.1 and T in [0.7, 1.3]: every velocity term of
+    the equilibrium is exercised.  FP64: 1e-14 of w_l.  FP32 deviations: the
+    FP64 value rounded once to FP32, so within 2^-24 of the deviation's size
+    plus the FP64 parity bar (1e-14 of max(w_l, |f_l|))."""
+    lx, ly = 37, 53
+    say(f"init with velocity {precision}")
+    rho = inputs.uniform_field(lx, ly, 61, 0.7, 1.3)
+    ux = inputs.uniform_field(lx, ly, 62, -0.1, 0.1)
+    uy = inputs.uniform_field(lx, ly, 63, -0.1, 0.1)
+    T = inputs.uniform_field(lx, ly, 64, 0.7, 1.3)
+    lat = Lattice(lx, ly, TAU, precision=precision, device=DEV)
+    lat.init(tg(rho), tg(ux), tg(uy), tg(T))
+    got = lat.get_pops().cpu().numpy().astype(np.float64)
+    ref = oracle.RefLattice(lx, ly, TAU)
+    ref.init(rho, ux, uy, T)
+    want = ref.get_pops()
+    if precision == "fp64":
+        err = relw(got, want)
+        say(f"  max |df|/w {err:.2e}")
+        assert err <= 1e-14
+    else:
+        dwant = want - WC
+        excess = np.abs(got - dwant) - (2.0 ** -24 * np.abs(dwant) + 1e-14 * np.maximum(WC, np.abs(want)))
+        say(f"  max |dd| {np.abs(got - dwant).max():.2e}, worst excess {excess.max():.2e}")
+        assert np.all(excess <= 0.0)
+    # the velocity terms matter: a u = 0 state differs by far more than the bar
+    assert np.max(np.abs(want - ref_rest(lx, ly, rho, T)) / WC) > 1e-2
+
+
+def ref_rest(lx, ly, rho, T):
+    r = oracle.RefLattice(lx, ly, TAU)
+    r.init(rho, 0.0, 0.0, T)
+    return r.get_pops()
+
+
+@pytest.mark.parametrize("step", ["split", "fused"])
+def test_set_tau_matches_oracle(step):
+    """lbm_set_tau between steps: 6 steps at tau = 0.7, then 6 at tau = 1.1,
+    against the oracle doing the same (a second oracle lattice at the new
+    tau continues from the first's state); an invalid tau is refused and
+    leaves the context's tau alone."""
+    lx, ly, g, t2 = 36, 41, -1e-4, 1.1
+    say(f"set_tau {step}")
+    P = inputs.rt_perturbation(lx, ly, 7)
+    lat = Lattice(lx, ly, TAU, g, TB, TT, step=step, device=DEV)
+    lat.init_rt(tg(P))
+    lat.step(6)
+    lat.set_tau(t2)
+    with pytest.raises(Exception):
+        lat.set_tau(0.5)
+    lat.step(6)
+    a, _ = oracle_rt(lx, ly, 7, 6, tau=TAU, g=g)
+    b = oracle.RefLattice(lx, ly, t2, g, TB, TT)
+    b.set_pops(a.get_pops())
+    b.step(6)
+    err = relw(lat.get_pops().cpu().numpy(), b.get_pops())
+    # the same run without the change differs by far more
+    a.step(6)
+    assert relw(a.get_pops(), b.get_pops()) > 1e-6
+    say(f"  err {err:.2e}")
+    assert err <= 1e-12
