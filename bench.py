@@ -306,11 +306,12 @@ def fp32_accuracy(args, nsteps=5000, every=500):
     return rows
 
 
-def adjoint_at_scale(lx=1024, ly=2048, nsteps=10000, budget=32 << 30, lam="fp64"):
+def adjoint_at_scale(lx=1024, ly=2048, nsteps=10000, budget=32 * 10 ** 9, lam="fp64"):
     """Gradient of 1/2 sum (T_N - T*)^2 w.r.t. the initial perturbation field
     P and tau on the 1024x2048 lattice, FP32 forward states, FP64 adjoint,
     binomial checkpointing; the job's peak device memory (workspace, stored
-    states, temporaries) stays inside `budget` bytes."""
+    states, temporaries) stays inside `budget` bytes (32 GB = 32e9 bytes,
+    which is also inside 32 GiB)."""
     import torch
 
     from paper_1703_04594_amd import inputs
@@ -364,13 +365,14 @@ def adjoint_at_scale(lx=1024, ly=2048, nsteps=10000, budget=32 << 30, lam="fp64"
     t_grad = time.perf_counter() - t0
     peak = torch.cuda.max_memory_allocated() - base_mem
     out = {"lattice": f"{lx}x{ly}", "steps": nsteps, "checkpoint": "binomial", "lambda": lam,
-           "budget_GB": round(budget / 2 ** 30, 1), "state_MB": round(state_bytes / 2 ** 20, 1),
+           "budget_bytes": budget, "state_bytes": state_bytes,
            "snapshot_slots": cfg.stats.get("slots"), "forward_steps_total": cfg.stats.get("forward_steps"),
            "adjoint_step_ms": round(t_adj * 1e3, 4), "forward_step_ms": round(t_step * 1e3, 4),
            "adjoint_over_forward_step": round(t_adj / t_step, 3),
            "forward_wall_s": round(t_fwd, 3), "gradient_wall_s": round(t_grad, 3),
            "gradient_over_forward_wall": round(t_grad / t_fwd, 3),
-           "peak_memory_GB": round(peak / 2 ** 30, 2), "loss": float(loss.detach()),
+           "peak_memory_bytes": peak, "peak_within_budget": bool(peak <= budget),
+           "workspace_bytes": ws_bytes, "loss": float(loss.detach()),
            "dL_dtau": float(tg.grad), "dL_dP_norm": float(Pg.grad.norm())}
     log(f"bench: adjoint at scale {out}")
     return out
