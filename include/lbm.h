@@ -26,8 +26,9 @@
  * Conventions
  *  - Every array pointer is a DEVICE pointer owned by the caller (for
  *    instance the data_ptr() of a torch tensor on the same device), unless a
- *    parameter says "host".  The library never allocates device memory: all
- *    of its buffers live in the caller's workspace.
+ *    parameter says "host".  Lattice contexts never allocate device memory:
+ *    all of their buffers live in the caller's workspace (the co-execution
+ *    calls and lbm_conservation_noalloc state their own exceptions).
  *  - Field arrays are [lx][ly], y fastest, FP64.
  *  - "Canonical" population arrays are [37][lx][ly], y fastest, in the storage
  *    precision: FP64 populations f_l for LBM_FP64; FP32 deviations
@@ -177,6 +178,29 @@ lbm_status lbm_step_state(lbm_ctx* ctx, void* src_state, void* dst_state);
  * fixed reduction order (bitwise reproducible): out4 = {sum rho, sum j_x,
  * sum j_y, sum E}, E = sum_l |xi_l|^2 f_l.  dev_out4: device FP64 [4]. */
 lbm_status lbm_conservation(lbm_ctx* ctx, double* dev_out4);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the totals
+ * of lbm_conservation for a canonical population array, with no context and
+ * no workspace.  The reduction's block partials live in a fixed device array
+ * of the library (1024 x 4 doubles = 32 KiB; each GPU the library runs on
+ * holds its own copy until the process ends); nothing is allocated per call
+ * and nothing needs clearing, since every partial is rewritten by each call.
+ * Calls that overlap on one GPU (different streams, or host threads) race on
+ * that array; calls are ordered by the stream.
+ *   precision:  lbm_precision of pops (FP64 f_l, or FP32 deviations f_l - w_l)
+ *   lx, ly:     >= 1 each, lx * ly <= LBM_NOALLOC_MAX_SITES (else LBM_ERR_SIZE)
+ *   pops:       device canonical [37][lx][ly] array, only read
+ *   dev_out4:   device FP64 [4] <- {sum rho, sum j_x, sum j_y, sum E}, with
+ *               the same kernels and reduction order as lbm_conservation, so
+ *               the two give bitwise equal totals for equal states
+ *   hip_stream: a stream of the current device (NULL: its null stream)
+ * Runs on the current device.  Errors: LBM_ERR_INVALID / LBM_ERR_SIZE before
+ * anything is launched, LBM_ERR_HIP for a failed lookup or launch; the
+ * message is lbm_last_error(NULL). */
+#define LBM_NOALLOC_MAX_SITES (1LL << 31)
+lbm_status lbm_conservation_noalloc(int precision, int lx, int ly, const void* pops, double* dev_out4,
+                                    void* hip_stream);
 
 /* ---- adjoint (requires params.adjoint != 0) ------------------------------- */
 /* The adjoint state lambda = dL/df (one value per population and site; stored

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "lbm.h"
@@ -435,6 +436,79 @@ lbm_status do_conservation(lbm_ctx* c, double* out4)
 }
 }  // namespace
 
+// ----------------------------------------------------------------------------
+// Scratch of lbm_conservation_noalloc: the reduction's block partials
+// (RED_BLOCKS x 4 doubles, 32 KiB) in a fixed device array instead of a
+// workspace.  In host code `scratch` names a host-side stand-in, not device
+// memory: its device address is looked up once per device with
+// hipGetSymbolAddress (that device current) and only that address reaches
+// kernels.  Every call on one device shares the array.
+// ----------------------------------------------------------------------------
+static __device__ __align__(256) double scratch[RED_BLOCKS * 4];
+
+namespace {
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[NOALLOC_MAX_DEVICES];   // device address of `scratch`, per device
+
+// Device address of `scratch` on the current device (looked up on the first
+// call there).
+lbm_status scratch_on_current_device(double** out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= NOALLOC_MAX_DEVICES) {
+        g_create_error = "conservation_noalloc: no usable current device";
+        return LBM_ERR_HIP;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            g_create_error = std::string("conservation_noalloc: hipGetSymbolAddress: ") + hipGetErrorString(e);
+            return LBM_ERR_HIP;
+        }
+        g_scratch_dev[dev] = static_cast<double*>(p);
+    }
+    *out = g_scratch_dev[dev];
+    return LBM_OK;
+}
+
+// Geometry of a canonical [37][lx][ly] array: no padding, no halos.
+Geo canonical_geo(int lx, int ly)
+{
+    Geo g{};
+    g.lx = lx;
+    g.ly = ly;
+    g.lyp = ly;
+    g.g = 0;
+    g.cs = ly;
+    g.ps = (long long)lx * ly;
+    g.origin = 0;
+    g.total = NPOP * g.ps;
+    return g;
+}
+
+template <typename S>
+lbm_status launch_conservation_noalloc(const Geo& g, const void* pops, double* part, double* out4, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_conservation_partial<S>), dim3(RED_BLOCKS), dim3(256), 0, st, (const S*)pops, g, part);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL((k_reduce_partials<4, false>), dim3(1), dim3(REDUCE_THREADS), 0, st,
+                           (const double*)part, RED_BLOCKS, out4);
+        e = hipGetLastError();
+    }
+    if (e != hipSuccess) {
+        g_create_error = std::string("conservation_noalloc: ") + hipGetErrorString(e);
+        return LBM_ERR_HIP;
+    }
+    return LBM_OK;
+}
+
+}  // namespace
+
 // ============================================================================
 // C ABI
 // ============================================================================
@@ -598,6 +672,34 @@ lbm_status lbm_conservation(lbm_ctx* c, double* dev_out4)
     if (!c) return LBM_ERR_INVALID;
     if (!dev_out4) return fail(c, LBM_ERR_INVALID, "conservation: NULL");
     return DISPATCH(c, do_conservation, dev_out4);
+}
+
+lbm_status lbm_conservation_noalloc(int precision, int lx, int ly, const void* pops, double* dev_out4,
+                                    void* hip_stream)
+{
+    if (precision != LBM_FP64 && precision != LBM_FP32_SHIFTED) {
+        g_create_error = "conservation_noalloc: unknown precision";
+        return LBM_ERR_INVALID;
+    }
+    if (lx < 1 || ly < 1) {
+        g_create_error = "conservation_noalloc: lx and ly must be >= 1";
+        return LBM_ERR_INVALID;
+    }
+    if ((long long)lx * ly > LBM_NOALLOC_MAX_SITES) {
+        g_create_error = "conservation_noalloc: lattice exceeds LBM_NOALLOC_MAX_SITES (2^31) sites";
+        return LBM_ERR_SIZE;
+    }
+    if (!pops || !dev_out4) {
+        g_create_error = "conservation_noalloc: NULL pointer";
+        return LBM_ERR_INVALID;
+    }
+    double* part = nullptr;
+    lbm_status s = scratch_on_current_device(&part);
+    if (s) return s;
+    const Geo g = canonical_geo(lx, ly);
+    const hipStream_t st = (hipStream_t)hip_stream;
+    return precision == LBM_FP64 ? launch_conservation_noalloc<double>(g, pops, part, dev_out4, st)
+                                 : launch_conservation_noalloc<float>(g, pops, part, dev_out4, st);
 }
 
 lbm_status lbm_sync(lbm_ctx* c)

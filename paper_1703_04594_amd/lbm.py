@@ -124,6 +124,8 @@ def lib() -> ctypes.CDLL:
     for n in ("lbm_host_pack", "lbm_host_unpack", "lbm_host_step", "lbm_hetero_create", "lbm_hetero_set_pops",
               "lbm_hetero_get_pops", "lbm_hetero_step", "lbm_hetero_times"):
         getattr(L, n).restype = st
+    L.lbm_conservation_noalloc.argtypes = [ci, ci, ci, vp, vp, vp]
+    L.lbm_conservation_noalloc.restype = st
     L.lbm_study_bytes.argtypes = [ci, ci, ci, ci]
     L.lbm_study_bytes.restype = ctypes.c_size_t
     for n in ("lbm_study_pack", "lbm_study_unpack", "lbm_study_propagate"):
@@ -328,6 +330,34 @@ class Lattice:
 
     def sync(self):
         self._check(self.L.lbm_sync(self.h), "sync")
+
+
+def conservation_noalloc(pops: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Lattice totals {sum rho, sum j_x, sum j_y, sum E} of a canonical
+    population tensor (37, lx, ly): float64 populations, or float32
+    deviations f - w (lbm_conservation_noalloc: the library allocates
+    nothing; `out`, a float64 (4,) tensor on the same device, may be given
+    so that this call allocates nothing either).  Runs on the tensor's device
+    and current stream."""
+    if pops.dtype == torch.float64:
+        prec = FP64
+    elif pops.dtype == torch.float32:
+        prec = FP32_SHIFTED
+    else:
+        raise ValueError("pops must be float64 or float32 (deviation form)")
+    if pops.dim() != 3 or pops.shape[0] != NPOP:
+        raise ValueError(f"expected a ({NPOP}, lx, ly) tensor, got {tuple(pops.shape)}")
+    _, lx, ly = pops.shape
+    _ptr(pops, pops.dtype, (NPOP, lx, ly), pops.device)
+    if out is None:
+        out = torch.empty(4, dtype=torch.float64, device=pops.device)
+    _ptr(out, torch.float64, (4,), pops.device)
+    with torch.cuda.device(pops.device):
+        st = lib().lbm_conservation_noalloc(prec, int(lx), int(ly), ctypes.c_void_p(pops.data_ptr()),
+                                            ctypes.c_void_p(out.data_ptr()), _stream(pops))
+    if st != 0:
+        raise LBMError(f"conservation_noalloc: {lib().lbm_last_error(None).decode()} (status {st})")
+    return out
 
 
 # ---------------------------------------------------------------------------

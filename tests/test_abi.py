@@ -23,7 +23,7 @@ def declared_functions():
 def test_every_declared_symbol_is_exported():
     L = lbm.lib()
     names = declared_functions()
-    assert len(names) == 46
+    assert len(names) == 47
     missing = [n for n in names if not hasattr(L, n)]
     assert not missing, missing
 
@@ -120,3 +120,19 @@ def test_layout_study_validates_arguments():
     assert L.lbm_study_propagate(1, 1, (1 << 26) // 7, 7, fake, ctypes.c_void_p(8192), None) == 2
     with pytest.raises(ValueError):
         lbm.study_bytes("aosoa", 1, 64, 96)
+
+
+def test_conservation_noalloc_validates_on_the_host():
+    """The no-allocation totals refuse a lattice beyond LBM_NOALLOC_MAX_SITES
+    (status 2), unknown precisions, empty lattices and NULL pointers (status
+    1), each with a message, before any HIP call."""
+    L = lbm.lib()
+    fake = ctypes.c_void_p(4096)
+    assert L.lbm_conservation_noalloc(0, 1 << 16, (1 << 15) + 1, fake, fake, None) == 2
+    assert b"exceeds" in L.lbm_last_error(None)
+    assert L.lbm_conservation_noalloc(2, 8, 8, fake, fake, None) == 1
+    assert b"precision" in L.lbm_last_error(None)
+    assert L.lbm_conservation_noalloc(1, 0, 8, fake, fake, None) == 1
+    assert L.lbm_conservation_noalloc(1, 8, 8, None, fake, None) == 1
+    assert L.lbm_conservation_noalloc(1, 8, 8, fake, None, None) == 1
+    assert b"NULL" in L.lbm_last_error(None)
