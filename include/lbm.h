@@ -32,7 +32,7 @@
  *  - Field arrays are [lx][ly], y fastest, FP64.
  *  - "Canonical" population arrays are [37][lx][ly], y fastest, in the storage
  *    precision: FP64 populations f_l for LBM_FP64; FP32 deviations
- *    f_l - w_l for LBM_FP32_SHIFTED.
+ *    f_l - w_l for both FP32 forms.
  *  - "State" arrays hold one population buffer in the library's internal
  *    padded layout (lbm_state_bytes bytes); they are opaque, for snapshots.
  *  - All calls enqueue work on the stream given to lbm_create and return
@@ -64,7 +64,13 @@ typedef enum {
     LBM_ERR_STATE = 4     /* call not allowed in the context's current state */
 } lbm_status;
 
-typedef enum { LBM_FP64 = 0, LBM_FP32_SHIFTED = 1 } lbm_precision;
+/* Population storage and collide arithmetic.  LBM_FP64: FP64 populations,
+ * FP64 arithmetic.  LBM_FP32_SHIFTED: FP32 deviations f_l - w_l from the
+ * rest state, collided in FP32 with the moment sums (37 terms each, before
+ * and after the relaxation) accumulated in FP64.  LBM_FP32_SHIFTED_F32SUMS:
+ * the same storage and collision with those sums in FP32 as well.  Both FP32
+ * forms keep FP64 for lbm_conservation and lbm_get_macros. */
+typedef enum { LBM_FP64 = 0, LBM_FP32_SHIFTED = 1, LBM_FP32_SHIFTED_F32SUMS = 2 } lbm_precision;
 typedef enum { LBM_Y_WALLS = 0, LBM_Y_PERIODIC = 1 } lbm_ybc;
 /* How x-periodicity reaches propagate: wrap the source column index inside the
  * kernel, or first copy 3-column halos (the in-GPU form of the paper's halo
@@ -188,7 +194,8 @@ lbm_status lbm_conservation(lbm_ctx* ctx, double* dev_out4);
  * and nothing needs clearing, since every partial is rewritten by each call.
  * Calls that overlap on one GPU (different streams, or host threads) race on
  * that array; calls are ordered by the stream.
- *   precision:  lbm_precision of pops (FP64 f_l, or FP32 deviations f_l - w_l)
+ *   precision:  lbm_precision of pops (FP64 f_l, or FP32 deviations f_l - w_l
+ *               for either FP32 form)
  *   lx, ly:     >= 1 each, lx * ly <= LBM_NOALLOC_MAX_SITES (else LBM_ERR_SIZE)
  *   pops:       device canonical [37][lx][ly] array, only read
  *   dev_out4:   device FP64 [4] <- {sum rho, sum j_x, sum j_y, sum E}, with

@@ -14,12 +14,61 @@
 //   multiple of 16.  Enqueued on hip_stream (a hipStream_t, 0 = default
 //   stream); returns without waiting.  Returns 0 on success, 1 for an invalid
 //   argument (nothing launched), 2 if the launch failed.
+//
+// The second probe is the fused step's own memory access pattern with no
+// arithmetic: on a padded columns-layout buffer of the library (the geometry
+// of lbm_kernels.hpp), every site gathers its 37 populations from
+// (x - e_x mod lx, y - e_y) and stores them at its own site, with the same
+// workgroups, block renumbering, load priority and store form as the FP64 /
+// FP32 fused step (walls and the collision left out).  It is the streaming
+// of eq. (4) evaluated per site, so dst equals a propagate of src.  Its time
+// is the ceiling that access pattern leaves the fused step.
+//
+// size_t cp_gather_bytes(int elem_bytes, int lx, int ly)
+//   bytes of one buffer (elem_bytes 8 or 4; lx, ly >= 7; lx ly <= 2^31),
+//   0 if invalid.
+// int cp_gather_copy(int elem_bytes, int lx, int ly, const void* src,
+//                    void* dst, void* hip_stream)
+//   src, dst: distinct device buffers of cp_gather_bytes bytes, 256-byte
+//   aligned.  Returns as cp_copy.
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
 #include <cstdint>
 
+#include "lbm_kernels.hpp"
+
 namespace {
+
+template <typename S>
+__global__ __launch_bounds__(lbm::SITE_THREADS) void k_gather_copy(const S* __restrict__ src, S* __restrict__ dst,
+                                                                  lbm::Geo g)
+{
+    using namespace lbm;
+    const SiteBlock sb = site_block<sizeof(S) == 8>(g);
+    const int x = sb.x, y = sb.y;
+    if (y >= g.ly) return;
+    const unsigned yb = (unsigned)y * (unsigned)sizeof(S);
+    S f[NPOP];
+    if constexpr (sizeof(S) == 8) __builtin_amdgcn_s_setprio(3);
+#pragma unroll
+    for (int l = 0; l < NPOP; ++l) {
+        const int xs = wrap_x(x - EX[l], g.lx);
+        f[l] = ld_at(src + (size_t)l * g.ps + g.origin + (long long)xs * g.cs - EY[l], yb);
+    }
+    if constexpr (sizeof(S) == 8) {
+        __builtin_amdgcn_sched_barrier(0);
+        __builtin_amdgcn_s_setprio(0);
+    }
+    S* col = dst + g.origin + (long long)x * g.cs;
+#pragma unroll
+    for (int l = 0; l < NPOP; ++l) st_nt(col + (size_t)l * g.ps, yb, f[l]);
+}
+
+bool gather_args_ok(int elem_bytes, int lx, int ly)
+{
+    return (elem_bytes == 8 || elem_bytes == 4) && lx >= 7 && ly >= 7 && (long long)lx * ly <= (1LL << 31);
+}
 
 typedef double v2 __attribute__((ext_vector_type(2)));
 
@@ -56,4 +105,31 @@ extern "C" int cp_copy(const void* src, void* dst, size_t bytes, int block_bytes
     case 4096: return launch<256>(src, dst, n, s);
     default: return 1;
     }
+}
+
+extern "C" size_t cp_gather_bytes(int elem_bytes, int lx, int ly)
+{
+    if (!gather_args_ok(elem_bytes, lx, ly)) return 0;
+    return (size_t)lbm::padded_geo(lx, ly, (size_t)elem_bytes, false).total * (size_t)elem_bytes;
+}
+
+extern "C" int cp_gather_copy(int elem_bytes, int lx, int ly, const void* src, void* dst, void* stream)
+{
+    if (!gather_args_ok(elem_bytes, lx, ly) || !src || !dst || src == dst ||
+        ((uintptr_t)src | (uintptr_t)dst) % 256 != 0)
+        return 1;
+    const lbm::Geo g = lbm::padded_geo(lx, ly, (size_t)elem_bytes, false);
+    const size_t bytes = (size_t)g.total * (size_t)elem_bytes;
+    const char* a = (const char*)src;
+    const char* b = (const char*)dst;
+    if (a < b + bytes && b < a + bytes) return 1;   // overlapping buffers
+    const dim3 grid((unsigned)((ly + lbm::SITE_THREADS - 1) / lbm::SITE_THREADS) * (unsigned)lx);
+    hipStream_t s = (hipStream_t)stream;
+    if (elem_bytes == 8)
+        hipLaunchKernelGGL((k_gather_copy<double>), grid, dim3(lbm::SITE_THREADS), 0, s, (const double*)src,
+                           (double*)dst, g);
+    else
+        hipLaunchKernelGGL((k_gather_copy<float>), grid, dim3(lbm::SITE_THREADS), 0, s, (const float*)src,
+                           (float*)dst, g);
+    return hipGetLastError() == hipSuccess ? 0 : 2;
 }

@@ -9,6 +9,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <type_traits>
 
 #include "lbm.h"
 #include "lbm_adjoint.hpp"
@@ -36,39 +37,15 @@ struct Plan {
     size_t total;
 };
 
-Geo make_geo(int lx, int ly, size_t elem, int layout)
-{
-    Geo g;
-    g.lx = lx;
-    g.ly = ly;
-    g.g = (int)(128 / elem);                             // 128-byte aligned row 0
-    const int col_align = (int)(128 / elem);
-    g.lyp = (int)align_up((size_t)ly + 2 * g.g, (size_t)col_align);
-    // An odd number of 128-byte lines per column segment.  With an even
-    // count, segment strides near a power of two (ly = 8192 in FP64: 514
-    // lines, 64 KiB + 256 B) slowed propagate from 6.3 to 5.3 TB/s; one more
-    // line restores it, and costs nothing measurable on other shapes.
-    if ((size_t)g.lyp * elem / 128 % 2 == 0) g.lyp += col_align;
-    const long long ncol = lx + 2 * HALO_X;
-    if (layout == LBM_LAYOUT_PLANES) {
-        g.cs = g.lyp;
-        g.ps = (long long)align_up((size_t)ncol * g.lyp * elem, ALIGN) / (long long)elem;
-        g.total = NPOP * g.ps;
-    } else {
-        g.ps = g.lyp;
-        g.cs = (long long)NPOP * g.lyp;
-        g.total = ncol * g.cs;
-    }
-    g.origin = (long long)HALO_X * g.cs + g.g;
-    return g;
-}
+Geo make_geo(int lx, int ly, size_t elem, int layout) { return padded_geo(lx, ly, elem, layout == LBM_LAYOUT_PLANES); }
 
 bool valid(const lbm_params* p)
 {
     if (!p) return false;
     if (p->lx < 7 || p->ly < 7) return false;
     if (!(p->tau > 0.5) || !std::isfinite(p->tau) || !std::isfinite(p->g_y)) return false;
-    if (p->precision != LBM_FP64 && p->precision != LBM_FP32_SHIFTED) return false;
+    if (p->precision != LBM_FP64 && p->precision != LBM_FP32_SHIFTED && p->precision != LBM_FP32_SHIFTED_F32SUMS)
+        return false;
     if (p->ybc != LBM_Y_WALLS && p->ybc != LBM_Y_PERIODIC) return false;
     if (p->xmode != LBM_X_WRAP && p->xmode != LBM_X_HALO) return false;
     if (p->step_kind != LBM_STEP_SPLIT && p->step_kind != LBM_STEP_FUSED) return false;
@@ -134,6 +111,7 @@ struct lbm_ctx {
     double* scratch2() { return partials() + (size_t)RED_BLOCKS * 4; }
     template <typename L> L* lam(int i) { return reinterpret_cast<L*>(ws + pl.off_lam[i]); }
     bool fp64() const { return p.precision == LBM_FP64; }
+    bool f32_sums() const { return p.precision == LBM_FP32_SHIFTED_F32SUMS; }
     bool lam32() const { return p.adjoint == 2; }
 };
 
@@ -265,28 +243,70 @@ lbm_status do_bc(lbm_ctx* c)
     return check_launch(c, "bc_apply");
 }
 
+// In-place collide of the current buffer; wo receives the wall densities
+// (WALLS) -- FP32 storage with FP32 sums takes the WIDE = false kernels.
+template <typename S, bool WALLS>
+void launch_collide(lbm_ctx* c, double* wo)
+{
+    const Geo& g = c->pl.geo;
+    if constexpr (std::is_same<S, float>::value) {
+        if (c->f32_sums()) {
+            hipLaunchKernelGGL((k_collide<S, WALLS, false>), site_grid(g), dim3(SITE_THREADS), 0, c->stream,
+                               (S*)c->buf(c->cur), g, c->cargs, wo);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((k_collide<S, WALLS, true>), site_grid(g), dim3(SITE_THREADS), 0, c->stream,
+                       (S*)c->buf(c->cur), g, c->cargs, wo);
+}
+
 template <typename S>
 lbm_status do_collide(lbm_ctx* c)
 {
-    const Geo& g = c->pl.geo;
     if (c->p.ybc == LBM_Y_WALLS) {
-        hipLaunchKernelGGL((k_collide<S, true>), site_grid(g), dim3(SITE_THREADS), 0, c->stream, (S*)c->buf(c->cur), g,
-                           c->cargs, c->wall_rho(1 - c->wr_cur));
+        launch_collide<S, true>(c, c->wall_rho(1 - c->wr_cur));
         lbm_status s = check_launch(c, "collide");
         if (s) return s;
         c->wr_cur = 1 - c->wr_cur;
         c->wr_buf = c->cur;
         return LBM_OK;
     }
-    hipLaunchKernelGGL((k_collide<S, false>), site_grid(g), dim3(SITE_THREADS), 0, c->stream, (S*)c->buf(c->cur), g,
-                       c->cargs, (double*)nullptr);
+    launch_collide<S, false>(c, (double*)nullptr);
     return check_launch(c, "collide");
+}
+
+// One fused step src -> dst (wall densities read from wr, written to wo).
+template <typename S, bool WIDE>
+void launch_fused_kernel(lbm_ctx* c, const S* src, S* dst, const double* wr, double* wo)
+{
+    const Geo& g = c->pl.geo;
+    const bool walls = c->p.ybc == LBM_Y_WALLS;
+    const bool wrap = c->p.xmode == LBM_X_WRAP;
+    if (wrap && walls)
+        hipLaunchKernelGGL((k_step_fused<S, true, true, WIDE>), site_grid(g), dim3(SITE_THREADS), 0, c->stream, src, dst, g, c->cargs, wr, c->wt, wo);
+    else if (wrap)
+        hipLaunchKernelGGL((k_step_fused<S, true, false, WIDE>), site_grid(g), dim3(SITE_THREADS), 0, c->stream, src, dst, g, c->cargs, wr, c->wt, wo);
+    else if (walls)
+        hipLaunchKernelGGL((k_step_fused<S, false, true, WIDE>), site_grid(g), dim3(SITE_THREADS), 0, c->stream, src, dst, g, c->cargs, wr, c->wt, wo);
+    else
+        hipLaunchKernelGGL((k_step_fused<S, false, false, WIDE>), site_grid(g), dim3(SITE_THREADS), 0, c->stream, src, dst, g, c->cargs, wr, c->wt, wo);
+}
+
+template <typename S>
+void launch_fused(lbm_ctx* c, const S* src, S* dst, const double* wr, double* wo)
+{
+    if constexpr (std::is_same<S, float>::value) {
+        if (c->f32_sums()) {
+            launch_fused_kernel<S, false>(c, src, dst, wr, wo);
+            return;
+        }
+    }
+    launch_fused_kernel<S, true>(c, src, dst, wr, wo);
 }
 
 template <typename S>
 lbm_status do_step_fused(lbm_ctx* c)
 {
-    const Geo& g = c->pl.geo;
     S* src = (S*)c->buf(c->cur);
     S* dst = (S*)c->buf(1 - c->cur);
     lbm_status s = launch_pre_stream<S>(c, src);
@@ -296,17 +316,7 @@ lbm_status do_step_fused(lbm_ctx* c)
         s = ensure_wall_density<S>(c, c->cur);
         if (s) return s;
     }
-    const bool wrap = c->p.xmode == LBM_X_WRAP;
-    const double* wr = c->wall_rho(c->wr_cur);
-    double* wo = c->wall_rho(1 - c->wr_cur);
-    if (wrap && walls)
-        hipLaunchKernelGGL((k_step_fused<S, true, true>), site_grid(g), dim3(SITE_THREADS), 0, c->stream, src, dst, g, c->cargs, wr, c->wt, wo);
-    else if (wrap)
-        hipLaunchKernelGGL((k_step_fused<S, true, false>), site_grid(g), dim3(SITE_THREADS), 0, c->stream, src, dst, g, c->cargs, wr, c->wt, wo);
-    else if (walls)
-        hipLaunchKernelGGL((k_step_fused<S, false, true>), site_grid(g), dim3(SITE_THREADS), 0, c->stream, src, dst, g, c->cargs, wr, c->wt, wo);
-    else
-        hipLaunchKernelGGL((k_step_fused<S, false, false>), site_grid(g), dim3(SITE_THREADS), 0, c->stream, src, dst, g, c->cargs, wr, c->wt, wo);
+    launch_fused<S>(c, src, dst, c->wall_rho(c->wr_cur), c->wall_rho(1 - c->wr_cur));
     s = check_launch(c, "step_fused");
     if (s) return s;
     c->cur = 1 - c->cur;
@@ -403,23 +413,14 @@ lbm_status do_get_state(lbm_ctx* c, char* dst)
 template <typename S>
 lbm_status do_step_state(lbm_ctx* c, char* src, char* dst)
 {
-    const Geo& g = c->pl.geo;
     S* sb = (S*)src;
     S* db = (S*)dst;
     lbm_status s = launch_pre_stream<S>(c, sb);   // padding of the source only
     if (s) return s;
     const bool walls = c->p.ybc == LBM_Y_WALLS;
-    const bool wrap = c->p.xmode == LBM_X_WRAP;
     const double* wr = walls ? (const double*)(src + c->pl.buf_bytes) : nullptr;
     double* wo = walls ? (double*)(dst + c->pl.buf_bytes) : nullptr;
-    if (wrap && walls)
-        hipLaunchKernelGGL((k_step_fused<S, true, true>), site_grid(g), dim3(SITE_THREADS), 0, c->stream, sb, db, g, c->cargs, wr, c->wt, wo);
-    else if (wrap)
-        hipLaunchKernelGGL((k_step_fused<S, true, false>), site_grid(g), dim3(SITE_THREADS), 0, c->stream, sb, db, g, c->cargs, wr, c->wt, wo);
-    else if (walls)
-        hipLaunchKernelGGL((k_step_fused<S, false, true>), site_grid(g), dim3(SITE_THREADS), 0, c->stream, sb, db, g, c->cargs, wr, c->wt, wo);
-    else
-        hipLaunchKernelGGL((k_step_fused<S, false, false>), site_grid(g), dim3(SITE_THREADS), 0, c->stream, sb, db, g, c->cargs, wr, c->wt, wo);
+    launch_fused<S>(c, sb, db, wr, wo);
     return check_launch(c, "step_state");
 }
 
@@ -677,7 +678,7 @@ lbm_status lbm_conservation(lbm_ctx* c, double* dev_out4)
 lbm_status lbm_conservation_noalloc(int precision, int lx, int ly, const void* pops, double* dev_out4,
                                     void* hip_stream)
 {
-    if (precision != LBM_FP64 && precision != LBM_FP32_SHIFTED) {
+    if (precision != LBM_FP64 && precision != LBM_FP32_SHIFTED && precision != LBM_FP32_SHIFTED_F32SUMS) {
         g_create_error = "conservation_noalloc: unknown precision";
         return LBM_ERR_INVALID;
     }

@@ -30,6 +30,36 @@ struct Geo {
 
 constexpr int HALO_X = 3;
 
+// Geometry of a padded population buffer of lx x ly sites with elem-byte
+// values: planes (structure of arrays) or columns layout.
+inline Geo padded_geo(int lx, int ly, size_t elem, bool planes)
+{
+    auto up = [](size_t v, size_t a) { return (v + a - 1) / a * a; };
+    Geo g;
+    g.lx = lx;
+    g.ly = ly;
+    g.g = (int)(128 / elem);                             // 128-byte aligned row 0
+    const int col_align = (int)(128 / elem);
+    g.lyp = (int)up((size_t)ly + 2 * g.g, (size_t)col_align);
+    // An odd number of 128-byte lines per column segment.  With an even
+    // count, segment strides near a power of two (ly = 8192 in FP64: 514
+    // lines, 64 KiB + 256 B) slowed propagate from 6.3 to 5.3 TB/s; one more
+    // line restores it, and costs nothing measurable on other shapes.
+    if ((size_t)g.lyp * elem / 128 % 2 == 0) g.lyp += col_align;
+    const long long ncol = lx + 2 * HALO_X;
+    if (planes) {
+        g.cs = g.lyp;
+        g.ps = (long long)up((size_t)ncol * g.lyp * elem, 256) / (long long)elem;
+        g.total = NPOP * g.ps;
+    } else {
+        g.ps = g.lyp;
+        g.cs = (long long)NPOP * g.lyp;
+        g.total = ncol * g.cs;
+    }
+    g.origin = (long long)HALO_X * g.cs + g.g;
+    return g;
+}
+
 struct HopTable { int ex[NPOP]; int ey[NPOP]; };
 constexpr HopTable make_hops()
 {
@@ -276,7 +306,8 @@ __device__ __forceinline__ void store_wall_density(const Cc (&f)[NPOP], const Ge
     }
 }
 
-template <typename S, bool WALLS>
+// WIDE = false: FP32 storage collided with FP32 moment sums (collide_site).
+template <typename S, bool WALLS, bool WIDE = true>
 __global__ __launch_bounds__(SITE_THREADS) void k_collide(S* __restrict__ buf, Geo g, CollideArgs args,
                                                        double* __restrict__ wall_rho_out)
 {
@@ -289,7 +320,7 @@ __global__ __launch_bounds__(SITE_THREADS) void k_collide(S* __restrict__ buf, G
     Cc f[NPOP];
 #pragma unroll
     for (int l = 0; l < NPOP; ++l) f[l] = (Cc)ld_nt(col + (size_t)l * g.ps, yb);
-    collide_site<Cc, Store<S>::shifted>(f, args);
+    collide_site<Cc, Store<S>::shifted, WIDE>(f, args);
 #pragma unroll
     for (int l = 0; l < NPOP; ++l) st_nt(col + (size_t)l * g.ps, yb, (S)f[l]);
     if (WALLS) store_wall_density<S>(f, g, x, y, wall_rho_out);
@@ -298,7 +329,7 @@ __global__ __launch_bounds__(SITE_THREADS) void k_collide(S* __restrict__ buf, G
 // ---------------------------------------------------------------------------
 // Fused step: gather (eq. (4) pull) + wall rule + collide, src -> dst.
 // ---------------------------------------------------------------------------
-template <typename S, bool WRAP, bool WALLS>
+template <typename S, bool WRAP, bool WALLS, bool WIDE = true>
 __global__ __launch_bounds__(SITE_THREADS) void k_step_fused(const S* __restrict__ src, S* __restrict__ dst, Geo g,
                                                           CollideArgs args, const double* __restrict__ wall_rho, WallTable wt,
                                                           double* __restrict__ wall_rho_out)
@@ -338,7 +369,7 @@ __global__ __launch_bounds__(SITE_THREADS) void k_step_fused(const S* __restrict
             }
         }
     }
-    collide_site<Cc, Store<S>::shifted>(f, args);
+    collide_site<Cc, Store<S>::shifted, WIDE>(f, args);
     S* col = dst + g.origin + (long long)x * g.cs;
 #pragma unroll
     for (int l = 0; l < NPOP; ++l) st_nt(col + (size_t)l * g.ps, yb, (S)f[l]);

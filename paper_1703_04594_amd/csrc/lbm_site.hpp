@@ -189,16 +189,22 @@ template <> __device__ __forceinline__ float arg_g<float>(const CollideArgs& a) 
 // sum w ex^2 = 1/c^2, sum w |e|^2 = 2/c^2, sum w |e|^4 = 8/c^4), which gives
 // a = 2 d0 - (c^2/2) d2, b = c^2 dx, c' = c^2 dy, d = -(c^2/2) d0 + (c^4/4) d2
 // for the moment defects (d0, dx, dy, d2).
-template <typename C, bool SHIFTED>
+//
+// WIDE = false (shifted form only) keeps every sum in FP32 as well: the
+// same collision with FP32 moment sums on both sides of the projection, for
+// measuring what the FP64 sums buy.
+template <typename C, bool SHIFTED, bool WIDE = true>
 __device__ __forceinline__ void collide_site(C (&f)[NPOP], const CollideArgs& args)
 {
     using K = ShellK<C>;
     const C omega = arg_omega<C>(args);
     C m0, sx, sy, s2;
     double m0d = 0.0, sxd = 0.0, syd = 0.0, s2d = 0.0;   // FP64 sums (shifted form)
-    if constexpr (SHIFTED) {
+    if constexpr (SHIFTED && WIDE) {
         hop_moments_wide(f, m0d, sxd, syd, s2d);
         m0 = (C)m0d; sx = (C)sxd; sy = (C)syd; s2 = (C)s2d;
+    } else if constexpr (SHIFTED) {
+        hop_moments<C>(f, m0, sx, sy, s2);
     } else {
         hop_moments<C>(f, m0, sx, sy, s2);
     }
@@ -254,13 +260,23 @@ __device__ __forceinline__ void collide_site(C (&f)[NPOP], const CollideArgs& ar
     }
     if constexpr (SHIFTED) {
         const C g = arg_g<C>(args);
-        double M0, MX, MY, M2;
-        hop_moments_wide(f, M0, MX, MY, M2);
         const C c2 = c2scale<C>();
-        const C d0 = (C)(m0d - M0);
-        const C dx = (C)(sxd - MX);
-        const C dy = (C)(syd + (1.0 + m0d) * (args.g / cscale<double>()) - MY);
-        const C d2 = (C)(s2d + (double)(rho * (C(2) * g * uy0 + g * g) / c2) - M2);
+        C d0, dx, dy, d2;
+        if constexpr (WIDE) {
+            double M0, MX, MY, M2;
+            hop_moments_wide(f, M0, MX, MY, M2);
+            d0 = (C)(m0d - M0);
+            dx = (C)(sxd - MX);
+            dy = (C)(syd + (1.0 + m0d) * (args.g / cscale<double>()) - MY);
+            d2 = (C)(s2d + (double)(rho * (C(2) * g * uy0 + g * g) / c2) - M2);
+        } else {
+            C M0, MX, MY, M2;
+            hop_moments<C>(f, M0, MX, MY, M2);
+            d0 = m0 - M0;
+            dx = sx - MX;
+            dy = sy + rho * (g / cscale<C>()) - MY;
+            d2 = s2 + rho * (C(2) * g * uy0 + g * g) / c2 - M2;
+        }
         const C ka = C(2) * d0 - C(0.5) * c2 * d2;
         const C kb = c2 * dx, kc = c2 * dy;
         const C kd = C(-0.5) * c2 * d0 + C(0.25) * c2 * c2 * d2;

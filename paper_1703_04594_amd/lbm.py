@@ -18,13 +18,15 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblbm.so")
 
 NPOP = 37
-FP64, FP32_SHIFTED = 0, 1
+FP64, FP32_SHIFTED, FP32_SHIFTED_F32SUMS = 0, 1, 2
 Y_WALLS, Y_PERIODIC = 0, 1
 X_WRAP, X_HALO = 0, 1
 STEP_SPLIT, STEP_FUSED = 0, 1
 LAYOUT_PLANES, LAYOUT_COLUMNS = 0, 1
 
-_PREC = {"fp64": FP64, "fp32": FP32_SHIFTED, "fp32_shifted": FP32_SHIFTED}
+# "fp32": FP32 deviations collided with FP64 moment sums; "fp32_f32sums":
+# the same with the sums in FP32 too
+_PREC = {"fp64": FP64, "fp32": FP32_SHIFTED, "fp32_shifted": FP32_SHIFTED, "fp32_f32sums": FP32_SHIFTED_F32SUMS}
 _YBC = {"walls": Y_WALLS, "periodic": Y_PERIODIC}
 _XMODE = {"wrap": X_WRAP, "halo": X_HALO}
 _STEP = {"split": STEP_SPLIT, "fused": STEP_FUSED}

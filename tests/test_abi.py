@@ -86,6 +86,21 @@ def test_reference_copy_library_rejects_bad_arguments():
     assert f(0x1008, 0x100000, 32, 2048, None) == 1            # misaligned source
     assert f(0x1000, 0x1010, 64, 2048, None) == 1              # overlapping ranges
     assert f(0x1000, 0x100000, 64, 3000, None) == 1            # unsupported workgroup size
+    # the fused step's access-pattern copy: sizes, and refusals before any launch
+    nb = lib.cp_gather_bytes
+    nb.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    nb.restype = ctypes.c_size_t
+    assert nb(8, 64, 48) > 37 * 70 * 48 * 8 and nb(4, 64, 48) > 0
+    assert nb(2, 64, 48) == 0 and nb(8, 6, 48) == 0 and nb(8, 1 << 16, (1 << 15) + 1) == 0
+    g = lib.cp_gather_copy
+    g.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    g.restype = ctypes.c_int
+    n = nb(8, 64, 48)
+    assert g(8, 64, 48, None, 0x100000, None) == 1                 # null source
+    assert g(8, 64, 48, 0x1000, 0x1000, None) == 1                 # same buffer
+    assert g(8, 64, 48, 0x1000, 0x1000 + n - 256, None) == 1       # overlapping buffers
+    assert g(8, 64, 48, 0x1008, 0x1000 + 2 * n, None) == 1         # not 256-byte aligned
+    assert g(3, 64, 48, 0x1000, 0x1000 + 2 * n, None) == 1         # element size
 
 
 def test_layout_study_validates_arguments():
@@ -130,7 +145,7 @@ def test_conservation_noalloc_validates_on_the_host():
     fake = ctypes.c_void_p(4096)
     assert L.lbm_conservation_noalloc(0, 1 << 16, (1 << 15) + 1, fake, fake, None) == 2
     assert b"exceeds" in L.lbm_last_error(None)
-    assert L.lbm_conservation_noalloc(2, 8, 8, fake, fake, None) == 1
+    assert L.lbm_conservation_noalloc(7, 8, 8, fake, fake, None) == 1
     assert b"precision" in L.lbm_last_error(None)
     assert L.lbm_conservation_noalloc(1, 0, 8, fake, fake, None) == 1
     assert L.lbm_conservation_noalloc(1, 8, 8, None, fake, None) == 1

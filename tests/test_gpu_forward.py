@@ -324,14 +324,16 @@ def test_uniform_rest_state_at_wall_temperature_stays():
 
 @pytest.mark.parametrize("step", ["split", "fused"])
 @pytest.mark.parametrize("layout", ["columns", "planes"])
-def test_fp32_shifted_against_fp64_oracle(step, layout):
+@pytest.mark.parametrize("precision", ["fp32", "fp32_f32sums"])
+def test_fp32_shifted_against_fp64_oracle(step, layout, precision):
     """FP32 deviations: per-field error after 50 steps of the 256x128 RT run.
     FP32 rounding of deviations O(0.3 w) is ~2e-8 of rho per step; the bound
-    below leaves an order of magnitude over 50 steps."""
+    below leaves an order of magnitude over 50 steps.  Both FP32 forms
+    (moment sums in FP64, and in FP32)."""
     lx, ly = 256, 128
-    say(f"fp32 RT {step}")
+    say(f"fp32 RT {step} {layout} {precision}")
     P = inputs.rt_perturbation(lx, ly, 1)
-    lat = Lattice(lx, ly, TAU, G, TB, TT, precision="fp32", step=step, layout=layout, device=DEV)
+    lat = Lattice(lx, ly, TAU, G, TB, TT, precision=precision, step=step, layout=layout, device=DEV)
     lat.init_rt(tg(P))
     lat.step(50)
     ref, _ = oracle_rt(lx, ly, 1, 50)
@@ -344,19 +346,22 @@ def test_fp32_shifted_against_fp64_oracle(step, layout):
     assert e_rho <= 1e-5 and e_T <= 1e-5 and e_u <= 1e-5
 
 
-def test_fp32_long_run_error_does_not_drift():
+@pytest.mark.parametrize("precision", ["fp32", "fp32_f32sums"])
+def test_fp32_long_run_error_does_not_drift(precision):
     """1000 steps of the 256x128 RT run in FP32 against the FP64 oracle.
     Deviations of size ~0.3 w stored in FP32 round at 2^-24 ~ 6e-8 of their
     size.  The non-conserved moments relax at rate 1/tau, so their error
     stays at that level; the conserved moments only take the storage
-    rounding of each step, unbiased, so at worst sqrt(1000) * 6e-8 ~ 2e-6.
-    Summing the 37 moment terms in FP32 instead would add a bias of ~2e-8
-    per step with a persistent sign (~2e-5 after 1000 steps), which this
-    bound rejects."""
+    rounding of each step, unbiased, so at worst sqrt(1000) * 6e-8 ~ 2e-6:
+    the bar of the default form, whose moment sums are FP64.  Summing the 37
+    moment terms in FP32 (the f32sums form) adds a bias of ~2e-8 per step
+    with a persistent sign at slowly changing sites, ~2e-5 after 1000 steps,
+    which the 2e-6 bar rejects; that form is held to 1e-4 (measured and
+    reported beside the default)."""
     lx, ly, n = 256, 128, 1000
-    say(f"fp32 long run {lx}x{ly} {n} steps")
+    say(f"fp32 long run {lx}x{ly} {n} steps {precision}")
     P = inputs.rt_perturbation(lx, ly, 1)
-    lat = Lattice(lx, ly, TAU, G, TB, TT, precision="fp32", step="fused", device=DEV)
+    lat = Lattice(lx, ly, TAU, G, TB, TT, precision=precision, step="fused", device=DEV)
     lat.init_rt(tg(P))
     lat.step(n)
     ref, _ = oracle_rt(lx, ly, 1, n, openmp=True)
@@ -366,7 +371,8 @@ def test_fp32_long_run_error_does_not_drift():
     e_T = np.max(np.abs(T - r_T) / r_T)
     e_u = max(np.max(np.abs(ux - r_ux)), np.max(np.abs(uy - r_uy)))
     say(f"fp32 {n}-step errors rho {e_rho:.2e} T {e_T:.2e} u {e_u:.2e}")
-    assert e_rho <= 2e-6 and e_T <= 2e-6 and e_u <= 2e-6
+    bar = 2e-6 if precision == "fp32" else 1e-4
+    assert e_rho <= bar and e_T <= bar and e_u <= bar
 
 
 def test_fp32_init_and_macros_are_fp64_exact_at_rest():
