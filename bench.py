@@ -165,6 +165,47 @@ def gather_copy_reference(lx, ly, stream, reps=20, runs=5):
     return out
 
 
+def adjoint_pattern_reference(lx, ly, stream, reps=20, runs=5):
+    """The reverse step's access pattern over FP32 states with no collide^T
+    arithmetic (cp_adjoint_pattern in csrc/copy_probe.hip: 37 gathered state
+    loads, 37 gathered lambda loads and 37 stores per site), for FP64 and FP32
+    lambda: median over `runs` runs of the mean time of `reps` launches, s."""
+    import ctypes
+
+    import numpy as np
+    import torch
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_1703_04594_amd", "libcopyprobe.so"))
+    lib.cp_gather_bytes.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    lib.cp_gather_bytes.restype = ctypes.c_size_t
+    vp = ctypes.c_void_p
+    lib.cp_adjoint_pattern.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, vp, vp]
+    lib.cp_adjoint_pattern.restype = ctypes.c_int
+    out = {}
+    nf = lib.cp_gather_bytes(4, lx, ly)
+    f_raw = torch.zeros(nf + 256, dtype=torch.uint8, device="cuda:0")
+    f = (f_raw.data_ptr() + 255) // 256 * 256
+    for lam_bytes in (8, 4):
+        nl = lib.cp_gather_bytes(lam_bytes, lx, ly)
+        l_raw = torch.zeros(nl + 256, dtype=torch.uint8, device="cuda:0")
+        m_raw = torch.empty(nl + 256, dtype=torch.uint8, device="cuda:0")
+        lp = (l_raw.data_ptr() + 255) // 256 * 256
+        mp = (m_raw.data_ptr() + 255) // 256 * 256
+
+        def go():
+            rc = lib.cp_adjoint_pattern(lam_bytes, lx, ly, f, lp, mp, stream.cuda_stream)
+            if rc:
+                raise RuntimeError(f"cp_adjoint_pattern failed ({rc})")
+        go()
+        stream.synchronize()
+        out["fp64" if lam_bytes == 8 else "fp32"] = float(np.median([time_launches(go, stream, reps)
+                                                                      for _ in range(runs)]))
+        del l_raw, m_raw
+        torch.cuda.empty_cache()
+    del f_raw
+    torch.cuda.empty_cache()
+    return out
+
+
 def run(args):
     import numpy as np
     import torch
@@ -261,10 +302,27 @@ def run(args):
         lat.step(1)
         dacc = torch.zeros((), dtype=torch.float64, device=dev)
         lat.seed_temperature(torch.ones((lx, ly), dtype=torch.float64, device=dev))
-        t_adj[lam] = time_launches(lambda: lat.adjoint_step(st, dacc), s, 10)
-        t_fwd32 = time_launches(lambda: lat.step(1), s, 10)
+        t_adj[lam] = float(np.median([time_launches(lambda: lat.adjoint_step(st, dacc), s, 10) for _ in range(5)]))
+        t_fwd32 = float(np.median([time_launches(lambda: lat.step(1), s, 10) for _ in range(5)]))
         del lat, st
         torch.cuda.empty_cache()
+
+    log("bench: x-periodicity by 3-column halos against the wrapped index")
+    xmode = {}
+    for prec, step in (("fp64", "fused"), ("fp64", "split"), ("fp32", "fused")):
+        row = {}
+        for xm in ("wrap", "halo"):
+            lat = Lattice(lx, ly, tau, g, tb, tt, precision=prec, step=step, xmode=xm, device=dev)
+            lat.init_rt(P)
+            lat.step(5)
+            row[xm] = float(np.median([time_launches(lambda: lat.step(1), s, 20) for _ in range(5)]))
+            del lat
+            torch.cuda.empty_cache()
+        xmode[f"{prec}_{step}"] = {"wrap_ms": round(row["wrap"] * 1e3, 4), "halo_ms": round(row["halo"] * 1e3, 4),
+                                   "halo_over_wrap": round(row["halo"] / row["wrap"], 4)}
+
+    log("bench: the reverse step's access pattern without arithmetic")
+    t_adj_pattern = adjoint_pattern_reference(lx, ly, s)
 
     bytes_fp64 = 2 * 37 * 8 * sites   # one read + one write of every population
     bytes_fp32 = 2 * 37 * 4 * sites
@@ -304,21 +362,27 @@ def run(args):
         "access_pattern_copy_ms": {k: round(v * 1e3, 4) for k, v in t_pattern.items()},
         "fused_over_access_pattern_copy": {"fp64": round(t_pattern["fp64"] / t_fused, 3),
                                            "fp32": round(t_pattern["fp32"] / t_fused32, 3)},
-        "kernel_times": "per-kernel figures: median of 5 runs of 20 back-to-back launches (HIP events)",
+        "x_halo_vs_wrap": xmode,
+        "adjoint_access_pattern_copy_ms": {k: round(v * 1e3, 4) for k, v in t_adj_pattern.items()},
+        "adjoint_over_access_pattern_copy": {"fp64_lambda": round(t_adj_pattern["fp64"] / t_adj["fp64"], 3),
+                                             "fp32_lambda": round(t_adj_pattern["fp32"] / t_adj["fp32"], 3)},
+        "adjoint_hbm_frac": {"fp64_lambda": round(740 * sites / t_adj["fp64"] / 1e9 / HBM_PEAK_GBS, 3),
+                             "fp32_lambda": round(444 * sites / t_adj["fp32"] / 1e9 / HBM_PEAK_GBS, 3)},
+        "kernel_times": "per-kernel figures: median of 5 runs of 10-20 back-to-back launches (HIP events)",
         "propagate_fp64_hbm_frac_runs": [round(bytes_fp64 / t / 1e9 / HBM_PEAK_GBS, 4) for t in t_prop_runs],
         "hbm_frac": {"fused_fp64": round(bytes_fp64 / t_fused / 1e9 / HBM_PEAK_GBS, 3),
                      "fused_fp32": round(bytes_fp32 / t_fused32 / 1e9 / HBM_PEAK_GBS, 3),
                      "propagate_fp64": round(bytes_fp64 / t_prop / 1e9 / HBM_PEAK_GBS, 3),
                      "collide_fp64": round(bytes_fp64 / t_coll / 1e9 / HBM_PEAK_GBS, 3)},
         "flop_frac": None if (lx, ly) != (2048, 4096) else {
-            "fused_fp64": flop_fraction("lbm::k_step_fused<double, true, true>", t_fused),
-            "collide_fp64": flop_fraction("lbm::k_collide<double, true>", t_coll),
-            "fused_fp32": flop_fraction("lbm::k_step_fused<float, true, true>", t_fused32),
+            "fused_fp64": flop_fraction("lbm::k_step_fused<double, true, true, true>", t_fused),
+            "collide_fp64": flop_fraction("lbm::k_collide<double, true, true>", t_coll),
+            "fused_fp32": flop_fraction("lbm::k_step_fused<float, true, true, true>", t_fused32),
             "adjoint_fp64_lambda": flop_fraction("lbm::k_adj_collide<float, double, true, true>", t_adj["fp64"]),
             "adjoint_fp32_lambda": flop_fraction("lbm::k_adj_collide<float, float, true, true>", t_adj["fp32"])},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic("lbm::k_step_fused<double, true, true>") if (lx, ly) == (2048, 4096) else None,
+                     "traffic": measured_traffic("lbm::k_step_fused<double, true, true, true>") if (lx, ly) == (2048, 4096) else None,
                      "kernel": "k_step_fused<double,wrap,walls>", "bytes_per_site": 592,
                      "algorithmic_bytes_per_launch": bytes_fp64},
     }
@@ -584,8 +648,8 @@ def hetero_study(lx=2048, ly=4096, steps=20):
     import torch
 
     from paper_1703_04594_amd import inputs
-    from paper_1703_04594_amd.hetero import autotune
-    from paper_1703_04594_amd.lbm import Hetero, Lattice
+    from paper_1703_04594_amd.hetero import Model, autotune
+    from paper_1703_04594_amd.lbm import Hetero, HostLattice, Lattice
 
     threads = min(16, os.cpu_count() or 1)
     dev = "cuda:0"
@@ -600,27 +664,52 @@ def hetero_study(lx=2048, ly=4096, steps=20):
         h.set_pops(f0)
         return h
 
-    model = autotune(make, lx, ly, m_probe=32, steps=steps)
-    log(f"bench: hetero model tau_d={model.tau_d:.3e} tau_h={model.tau_h:.3e} t_swap={model.t_swap:.3e}")
+    widths = [m for m in (2, 4, 8, 16, 32, 64, 128) if lx - 2 * m >= 3]
+
+    def host_probe(m):
+        """Host step seconds of the host part of an m-column split alone: its
+        band of 2m columns plus 3 halo columns per side (lbm_host_step)."""
+        hl = HostLattice(2 * m + 6, ly, 0.7, -1e-5, 4 / 3, 2 / 3, threads=threads)
+        hl.set_pops(f0[:, :2 * m + 6])
+        hl.step(3)
+        t0 = time.perf_counter()
+        hl.step(steps)
+        return (time.perf_counter() - t0) / steps
+
+    model = autotune(make, lx, ly, m_probe=32, steps=steps, host_probe=host_probe, host_widths=widths)
+    single = Model(model.tau_d, model.tau_h, model.t_swap)    # the paper's form: one tau_h (m = 32)
+    log(f"bench: hetero model tau_d={model.tau_d:.3e} tau_h={model.tau_h:.3e} t_swap={model.t_swap:.3e} "
+        f"host_times={model.host_times}")
     sweep = []
-    for m in (0, 2, 4, 8, 16, 32, 64, 128):
-        if lx - 2 * m < 3:
-            continue
+    for m in [0] + widths:
         h = make(m)
         h.step(3)
         h.step(steps)
         t = h.times()
         h.close()
-        row = {"m": m, "host_fraction": round(2 * m / lx, 4),
-               "mlups": round(lx * ly / t["wall"] / 1e6, 1),
-               "model_mlups": round(model.mlups(lx, ly, m), 1),
+        meas = lx * ly / t["wall"] / 1e6
+        p1, p2 = single.mlups(lx, ly, m), model.mlups(lx, ly, m)
+        # the model's composition max(T_acc, T_host) + T_swap fed with this
+        # run's own component times: checks the overlap assumption alone
+        p3 = lx * ly / (max(t["gpu"], t["host"]) + t["swap"]) / 1e6
+        row = {"m": m, "host_fraction": round(2 * m / lx, 4), "mlups": round(meas, 1),
+               "model_mlups": round(p1, 1), "model_rel_err": round(p1 / meas - 1, 4),
+               "model_host_times_mlups": round(p2, 1), "model_host_times_rel_err": round(p2 / meas - 1, 4),
+               "composition_rel_err": round(p3 / meas - 1, 4),
+               "host_ns_per_site": None if m == 0 else round(t["host"] / (2 * m * ly) * 1e9, 4),
+               "host_alone_ms": None if m == 0 else round(model.host_times[m] * 1e3, 4),
                "ms": {k: round(v * 1e3, 4) for k, v in t.items()}}
         sweep.append(row)
         log(f"bench: hetero {row}")
     return {"lattice": f"{lx}x{ly}", "precision": "fp64", "host_threads": threads, "steps": steps,
             "tau_d_ns_per_site": round(model.tau_d * 1e9, 5), "tau_h_ns_per_site": round(model.tau_h * 1e9, 4),
-            "t_swap_ms": round(model.t_swap * 1e3, 4), "m_balance": round(model.m_balance(lx), 2),
-            "best_m": model.best_m(lx, ly), "sweep": sweep}
+            "tau_h_ns_per_site_by_m": {m: round(v / (2 * m * ly) * 1e9, 4) for m, v in model.host_times.items()},
+            "t_swap_ms": round(model.t_swap * 1e3, 4), "m_balance": round(single.m_balance(lx), 2),
+            "best_m": single.best_m(lx, ly), "best_m_host_times": model.best_m(lx, ly),
+            "max_abs_rel_err": {"model": max(abs(r["model_rel_err"]) for r in sweep),
+                                "model_host_times": max(abs(r["model_host_times_rel_err"]) for r in sweep),
+                                "composition": max(abs(r["composition_rel_err"]) for r in sweep)},
+            "sweep": sweep}
 
 
 def profile_workload(args):
@@ -667,7 +756,106 @@ def profile_workload(args):
             lat.adjoint_step(st, dacc)
         torch.cuda.synchronize()
         del lat, st
+    lat = Lattice(lx, ly, 0.7, -1e-5, 4 / 3, 2 / 3, precision="fp32_f32sums", step="fused", device=dev)
+    lat.init_rt(P)
+    lat.step(args.steps)
+    torch.cuda.synchronize()
+    del lat
+    torch.cuda.empty_cache()
+    s = torch.cuda.current_stream()
+    gather_copy_reference(lx, ly, s, reps=args.steps, runs=1)
+    adjoint_pattern_reference(lx, ly, s, reps=args.steps, runs=1)
+    torch.cuda.synchronize()
     print(json.dumps({"profile_workload": "done", "steps": args.steps}), flush=True)
+
+
+def _csv_rows(d, suffix):
+    import csv
+    import glob
+    rows = []
+    for path in sorted(glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True)):
+        with open(path, newline="") as fh:
+            rows.extend(csv.DictReader(fh))
+    if not rows:
+        raise SystemExit(f"no *{suffix} under {d}")
+    return rows
+
+
+def _short(name):
+    """Kernel name without its return type and argument list."""
+    name = name.replace("(anonymous namespace)::", "")
+    depth, out = 0, []
+    for ch in name:
+        if ch == "(" and depth == 0:
+            break
+        depth += ch == "<"
+        depth -= ch == ">"
+        out.append(ch)
+    s = "".join(out).strip()
+    return s[5:] if s.startswith("void ") else s
+
+
+def summarize_counters(trace_dir, fetch_dir, write_dir, f64_dir, f32_dir, lx, ly):
+    """Per-kernel averages from rocprofv3 runs of `bench.py --profile`
+    (kernel-trace stats, FETCH_SIZE, WRITE_SIZE, and the FP64 / FP32 VALU
+    instruction counters), written to profiles/d2q37_<lx>x<ly>_counters.json
+    with the current kernel-source hash.  FETCH_SIZE and WRITE_SIZE (KiB per
+    dispatch) are scaled by what they read for the workload's first kernel,
+    a plain 1 GiB copy (2^30 bytes each way)."""
+    from collections import defaultdict
+    stats = {_short(r["Name"]): float(r["AverageNs"]) for r in _csv_rows(trace_dir, "kernel_stats.csv")}
+
+    def per_kernel(d):
+        acc = defaultdict(lambda: defaultdict(list))
+        order = []
+        for r in sorted(_csv_rows(d, "counter_collection.csv"), key=lambda r: int(r["Dispatch_Id"])):
+            k = _short(r["Kernel_Name"])
+            if k not in acc:
+                order.append(k)
+            acc[k][r["Counter_Name"]].append(float(r["Counter_Value"]))
+        return acc, order
+
+    def avg(acc):
+        return {k: {c: sum(v) / len(v) for c, v in cs.items()} for k, cs in acc.items()}
+
+    fetch_all, order = per_kernel(fetch_dir)
+    write_all, _ = per_kernel(write_dir)
+    # calibration: the three 1 GiB device-to-device copies that start the
+    # workload (the runtime's copy kernel), first in dispatch order
+    copy = "__amd_rocclr_copyBuffer"
+    fscale = 2 ** 30 / (sum(fetch_all[copy]["FETCH_SIZE"][:3]) / 3 * 1024)
+    wscale = 2 ** 30 / (sum(write_all[copy]["WRITE_SIZE"][:3]) / 3 * 1024)
+    fetch, write = avg(fetch_all), avg(write_all)
+    f64, f32 = avg(per_kernel(f64_dir)[0]), avg(per_kernel(f32_dir)[0])
+    sites = lx * ly
+    alg = {"k_step_fused<double": 592, "k_step_fused<float": 296, "k_propagate<double": 592,
+           "k_propagate<float": 296, "k_collide<double": 592, "k_collide<float": 296, "k_gather_copy<double": 592,
+           "k_gather_copy<float": 296, "k_adj_collide<float, double": 740, "k_adj_collide<float, float": 444,
+           "k_adjoint_pattern<double": 740, "k_adjoint_pattern<float": 444}
+    out = {"workload": f"{lx}x{ly} Rayleigh-Taylor, columns layout", "fetch_scale": round(fscale, 4),
+           "write_scale": round(wscale, 4), "calibration": f"first three {copy} dispatches, 1 GiB each way",
+           "flops_note": "flops_* = 64 x SQ_INSTS_VALU_FLOPS_FP64/FP32 (wave-instruction counts, FMA as 2), per launch",
+           "source_sha256": kernel_source_sha256(), "kernels": {}}
+    for k in order:
+        rb = fetch[k]["FETCH_SIZE"] * 1024 * fscale
+        wb = write.get(k, {}).get("WRITE_SIZE", 0.0) * 1024 * wscale
+        row = {"read_bytes": int(rb), "write_bytes": int(wb), "traffic_bytes": int(rb + wb),
+               "avg_ns": stats.get(k)}
+        for key, b in alg.items():
+            if key in k:
+                row["algorithmic_bytes"] = b * sites
+                row["traffic_over_algorithmic"] = round((rb + wb) / (b * sites), 4)
+        if k in f64:
+            row["flops_fp64"] = int(64 * f64[k].get("SQ_INSTS_VALU_FLOPS_FP64", 0))
+            row["valu_f64_instr"] = {n: int(f64[k].get(f"SQ_INSTS_VALU_{n}_F64", 0)) for n in ("ADD", "MUL", "FMA", "TRANS")}
+        if k in f32:
+            row["flops_fp32"] = int(64 * f32[k].get("SQ_INSTS_VALU_FLOPS_FP32", 0))
+            row["valu_f32_instr"] = {n: int(f32[k].get(f"SQ_INSTS_VALU_{n}_F32", 0)) for n in ("ADD", "MUL", "FMA", "TRANS")}
+        out["kernels"][k] = row
+    path = os.path.join(ROOT, "profiles", f"d2q37_{lx}x{ly}_counters.json")
+    with open(path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps({"summary": path, "kernels": len(order)}), flush=True)
 
 
 def main():
@@ -687,6 +875,9 @@ def main():
                          "(one JSON line)")
     ap.add_argument("--hetero-size", default="1024x2048,2048x4096,2160x8192",
                     help="lattices for --hetero, as LXxLY[,LXxLY...]")
+    ap.add_argument("--summarize-counters", nargs=5, metavar=("TRACE", "FETCH", "WRITE", "F64", "F32"),
+                    help="write profiles/d2q37_<lx>x<ly>_counters.json from rocprofv3 output directories of "
+                         "`bench.py --profile` (kernel-trace stats, FETCH_SIZE, WRITE_SIZE, FP64 and FP32 VALU passes)")
     ap.add_argument("--layout-study", action="store_true",
                     help="per-kernel FP64 times on the 2160x8192 lattice for each layout (one JSON line)")
     args = ap.parse_args()
@@ -694,6 +885,9 @@ def main():
         print("bench.py: runs on one GPU only; multi-GPU X-slab sharding is not implemented",
               file=sys.stderr)
         sys.exit(2)
+    if args.summarize_counters:
+        summarize_counters(*args.summarize_counters, args.lx, args.ly)
+        return
     if args.profile:
         profile_workload(args)
         return

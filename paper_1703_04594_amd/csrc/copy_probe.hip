@@ -24,6 +24,13 @@
 // of eq. (4) evaluated per site, so dst equals a propagate of src.  Its time
 // is the ceiling that access pattern leaves the fused step.
 //
+// The third probe is the reverse step's access pattern over FP32 states: per
+// site, 37 populations gathered from (x - e_x, y - e_y) of an FP32 state
+// buffer, 37 gathered from (x + e_x, y + e_y) of a lambda buffer (FP32 or
+// FP64), and mu_l = f_l + lambda_l stored at the site, with the reverse
+// step's workgroups and block renumbering (the collide^T arithmetic and the
+// wall terms left out).
+//
 // size_t cp_gather_bytes(int elem_bytes, int lx, int ly)
 //   bytes of one buffer (elem_bytes 8 or 4; lx, ly >= 7; lx ly <= 2^31),
 //   0 if invalid.
@@ -31,6 +38,11 @@
 //                    void* dst, void* hip_stream)
 //   src, dst: distinct device buffers of cp_gather_bytes bytes, 256-byte
 //   aligned.  Returns as cp_copy.
+// int cp_adjoint_pattern(int lam_bytes, int lx, int ly, const void* f,
+//                        const void* lam, void* mu, void* hip_stream)
+//   f: cp_gather_bytes(4, lx, ly) bytes; lam, mu: cp_gather_bytes(lam_bytes,
+//   lx, ly) bytes each (lam_bytes 4 or 8); three distinct 256-byte aligned
+//   device buffers.  Returns as cp_copy.
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
@@ -63,6 +75,31 @@ __global__ __launch_bounds__(lbm::SITE_THREADS) void k_gather_copy(const S* __re
     S* col = dst + g.origin + (long long)x * g.cs;
 #pragma unroll
     for (int l = 0; l < NPOP; ++l) st_nt(col + (size_t)l * g.ps, yb, f[l]);
+}
+
+template <typename L>
+__global__ __launch_bounds__(lbm::SITE_THREADS) void k_adjoint_pattern(const float* __restrict__ f,
+                                                                      const L* __restrict__ lam, L* __restrict__ mu,
+                                                                      lbm::Geo g, lbm::Geo lg)
+{
+    using namespace lbm;
+    const SiteBlock sb = site_block(g);
+    const int x = sb.x, y = sb.y;
+    if (y >= g.ly) return;
+    const unsigned yb = (unsigned)y * 4u, yd = (unsigned)y * (unsigned)sizeof(L);
+    float gl[NPOP];
+    L la[NPOP];
+#pragma unroll
+    for (int l = 0; l < NPOP; ++l) {
+        la[l] = ld_at(lam + (size_t)l * lg.ps + lg.origin + (long long)wrap_x(x + EX[l], lg.lx) * lg.cs + EY[l], yd);
+    }
+#pragma unroll
+    for (int l = 0; l < NPOP; ++l) {
+        gl[l] = ld_at(f + (size_t)l * g.ps + g.origin + (long long)wrap_x(x - EX[l], g.lx) * g.cs - EY[l], yb);
+    }
+    L* mcol = mu + lg.origin + (long long)x * lg.cs;
+#pragma unroll
+    for (int l = 0; l < NPOP; ++l) st_nt(mcol + (size_t)l * lg.ps, yd, (L)(la[l] + (L)gl[l]));
 }
 
 bool gather_args_ok(int elem_bytes, int lx, int ly)
@@ -131,5 +168,31 @@ extern "C" int cp_gather_copy(int elem_bytes, int lx, int ly, const void* src, v
     else
         hipLaunchKernelGGL((k_gather_copy<float>), grid, dim3(lbm::SITE_THREADS), 0, s, (const float*)src,
                            (float*)dst, g);
+    return hipGetLastError() == hipSuccess ? 0 : 2;
+}
+
+extern "C" int cp_adjoint_pattern(int lam_bytes, int lx, int ly, const void* f, const void* lam, void* mu,
+                                  void* stream)
+{
+    if (!gather_args_ok(lam_bytes, lx, ly) || !f || !lam || !mu || f == lam || f == mu || lam == mu ||
+        ((uintptr_t)f | (uintptr_t)lam | (uintptr_t)mu) % 256 != 0)
+        return 1;
+    const lbm::Geo g = lbm::padded_geo(lx, ly, 4, false);
+    const lbm::Geo lg = lbm::padded_geo(lx, ly, (size_t)lam_bytes, false);
+    const size_t nf = (size_t)g.total * 4, nl = (size_t)lg.total * (size_t)lam_bytes;
+    auto overlap = [](const void* p, size_t n, const void* q, size_t m) {
+        const char* a = (const char*)p;
+        const char* b = (const char*)q;
+        return a < b + m && b < a + n;
+    };
+    if (overlap(f, nf, lam, nl) || overlap(f, nf, mu, nl) || overlap(lam, nl, mu, nl)) return 1;
+    const dim3 grid((unsigned)((ly + lbm::SITE_THREADS - 1) / lbm::SITE_THREADS) * (unsigned)lx);
+    hipStream_t s = (hipStream_t)stream;
+    if (lam_bytes == 8)
+        hipLaunchKernelGGL((k_adjoint_pattern<double>), grid, dim3(lbm::SITE_THREADS), 0, s, (const float*)f,
+                           (const double*)lam, (double*)mu, g, lg);
+    else
+        hipLaunchKernelGGL((k_adjoint_pattern<float>), grid, dim3(lbm::SITE_THREADS), 0, s, (const float*)f,
+                           (const float*)lam, (float*)mu, g, lg);
     return hipGetLastError() == hipSuccess ? 0 : 2;
 }

@@ -38,9 +38,12 @@ def draw_cases(n, seed=20170313):
 
 
 CASES = draw_cases(40)
+# the FP32 form with FP32 moment sums, on its own draws (same bars as FP32)
+CASES_F32SUMS = [dict(c, precision="fp32_f32sums") for c in draw_cases(12, seed=20170315)]
 
 
-@pytest.mark.parametrize("case", CASES, ids=[f"{i}" for i in range(len(CASES))])
+@pytest.mark.parametrize("case", CASES + CASES_F32SUMS,
+                         ids=[f"{i}" for i in range(len(CASES))] + [f"f32sums-{i}" for i in range(len(CASES_F32SUMS))])
 def test_random_configuration_matches_oracle(case):
     c = case
     say(f"random case {c}")

@@ -43,3 +43,22 @@ def test_best_m():
         b = mod.best_m(lx, ly)
         others = [0] + list(range(2, (lx - 3) // 2 + 1))
         assert mod.t_exe(lx, ly, b) <= min(mod.t_exe(lx, ly, m) for m in others) * (1 + 1e-12)
+
+
+def test_measured_host_times():
+    """T_host(m) from host-only runs: exact at the measured widths, linear
+    between them, the nearest width's per-site rate beyond them; best_m
+    then searches every admissible m, and no admissible m beats it."""
+    lx, ly = 2048, 4096
+    ht = {2: 0.15e-3, 8: 0.32e-3, 32: 0.83e-3, 128: 3.38e-3}
+    mod = Model(tau_d=1.04e-10, tau_h=3.0e-9, t_swap=0.13e-3, host_times=ht)
+    for m, t in ht.items():
+        assert mod.t_host(ly, m) == pytest.approx(t)
+    assert mod.t_host(ly, 20) == pytest.approx(0.32e-3 + (0.83e-3 - 0.32e-3) * 12 / 24)
+    assert mod.t_host(ly, 256) == pytest.approx(3.38e-3 * 2)
+    assert mod.t_exe(lx, ly, 32) == pytest.approx(max((lx - 64) * ly * 1.04e-10, 0.83e-3) + 0.13e-3)
+    b = mod.best_m(lx, ly)
+    others = [0] + list(range(2, (lx - 3) // 2 + 1))
+    assert mod.t_exe(lx, ly, b) <= min(mod.t_exe(lx, ly, m) for m in others)
+    # with one tau_h and no host times the closed form is unchanged
+    assert Model(1.04e-10, 3.0e-9, 0.13e-3).t_host(ly, 32) == pytest.approx(64 * ly * 3.0e-9)
