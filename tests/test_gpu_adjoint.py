@@ -371,3 +371,25 @@ def test_set_tau_applies_to_the_reverse_step():
         lat.adjoint_step(st, dacc)
         out.append((lat.get_lambda(), dacc))
     assert torch.equal(out[0][0], out[1][0]) and torch.equal(out[0][1], out[1][1])
+
+
+def test_reverse_step_over_f32sums_states_equals_fp32():
+    """The reverse step linearises the exact step around the stored FP32
+    deviations, whichever sums the forward used: over the same stored state
+    and lambda, a context of the FP32-sums form gives bitwise the FP32 form's
+    lambda_n and d/dtau term."""
+    lx, ly, g = 24, 20, -1e-3
+    say("adjoint over f32sums states")
+    noise = torch.tensor(inputs.population_noise(lx, ly, 81))
+    lam1 = torch.tensor(inputs.population_noise(lx, ly, 82))
+    f_store = (WT[:, None, None] * 0.05 * noise).to(torch.float32).to(DEV)
+    out = []
+    for prec in ("fp32", "fp32_f32sums"):
+        lat = Lattice(lx, ly, TAU, g, TB, TT, precision=prec, adjoint=True, device=DEV)
+        lat.set_pops(f_store)
+        st = lat.get_state()
+        lat.set_lambda(lam1.to(DEV))
+        dacc = torch.zeros((), dtype=torch.float64, device=DEV)
+        lat.adjoint_step(st, dacc)
+        out.append((lat.get_lambda(), dacc))
+    assert torch.equal(out[0][0], out[1][0]) and torch.equal(out[0][1], out[1][1])

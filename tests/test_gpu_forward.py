@@ -226,7 +226,7 @@ def test_zero_steps_change_nothing(precision):
     assert torch.equal(lat.get_pops(), before)
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32_f32sums"])
 @pytest.mark.parametrize("ybc,xmode", [("walls", "wrap"), ("periodic", "wrap"), ("walls", "halo")])
 def test_step_state_equals_step(precision, ybc, xmode):
     """lbm_step_state (snapshot to snapshot) gives bitwise the state that
