@@ -518,6 +518,60 @@ def adjoint_at_scale(lx=1024, ly=2048, nsteps=10000, budget=32 * 10 ** 9, lam="f
     return out
 
 
+def adjoint_c4(lx=512, ly=512, nsteps=2000, lam="fp64"):
+    """The adjoint configuration's own lattice: 512x512, FP32 forward, FP64
+    (or FP32) lambda, 2000 steps, sqrt(T) checkpointing, loss 1/2 sum (T_N -
+    T*)^2 with T* the final temperature of the seed-2 run: per-step adjoint /
+    forward time and the whole gradient's wall time over the forward's."""
+    import numpy as np
+    import torch
+
+    from paper_1703_04594_amd import inputs
+    from paper_1703_04594_amd.autograd import RolloutConfig, rt_temperature
+    from paper_1703_04594_amd.lbm import Lattice
+
+    dev = "cuda:0"
+    P = torch.tensor(inputs.rt_perturbation(lx, ly, 1), device=dev)
+    lat = Lattice(lx, ly, 0.7, -1e-5, 4 / 3, 2 / 3, precision="fp32", step="fused", device=dev)
+    lat.init_rt(torch.tensor(inputs.rt_perturbation(lx, ly, 2), device=dev))
+    lat.step(nsteps)
+    Tt = lat.macros()[3].clone()
+    lat.init_rt(P)
+    lat.step(10)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat.step(nsteps)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    del lat
+    probe = Lattice(lx, ly, 0.7, -1e-5, 4 / 3, 2 / 3, precision="fp32", step="fused", adjoint=lam, device=dev)
+    probe.init_rt(P)
+    st = probe.get_state()
+    probe.step(1)
+    probe.seed_temperature(torch.ones((lx, ly), dtype=torch.float64, device=dev))
+    dacc = torch.zeros((), dtype=torch.float64, device=dev)
+    t_adj = float(np.median([time_launches(lambda: probe.adjoint_step(st, dacc), probe.stream, 50) for _ in range(5)]))
+    t_step = float(np.median([time_launches(lambda: probe.step(1), probe.stream, 50) for _ in range(5)]))
+    del probe, st
+    cfg = RolloutConfig(lx, ly, nsteps, precision="fp32", checkpoint="sqrt", lambda_precision=lam)
+    for rep in range(2):          # the first rollout pays one-time costs
+        Pg = P.clone().requires_grad_(True)
+        tg = torch.tensor(0.7, dtype=torch.float64, device=dev, requires_grad=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        T = rt_temperature(Pg, tg, cfg)
+        (0.5 * ((T - Tt) ** 2).sum()).backward()
+        torch.cuda.synchronize()
+        t_grad = time.perf_counter() - t0
+    out = {"lattice": f"{lx}x{ly}", "steps": nsteps, "checkpoint": "sqrt", "lambda": lam,
+           "adjoint_step_ms": round(t_adj * 1e3, 4), "forward_step_ms": round(t_step * 1e3, 4),
+           "adjoint_over_forward_step": round(t_adj / t_step, 3), "forward_wall_s": round(t_fwd, 4),
+           "gradient_wall_s": round(t_grad, 4), "gradient_over_forward_wall": round(t_grad / t_fwd, 3),
+           "forward_steps_total": cfg.stats.get("forward_steps"), "snapshot_slots": cfg.stats.get("slots")}
+    log(f"bench: adjoint 512x512 {out}")
+    return out
+
+
 def cpu_baseline(args, budget_s=15.0):
     """The oracle (OpenMP build of the plain C source) on the host cores, on a
     bounded number of steps of the same lattice."""
@@ -878,6 +932,8 @@ def main():
     ap.add_argument("--summarize-counters", nargs=5, metavar=("TRACE", "FETCH", "WRITE", "F64", "F32"),
                     help="write profiles/d2q37_<lx>x<ly>_counters.json from rocprofv3 output directories of "
                          "`bench.py --profile` (kernel-trace stats, FETCH_SIZE, WRITE_SIZE, FP64 and FP32 VALU passes)")
+    ap.add_argument("--fp32-accuracy", type=int, metavar="STEPS",
+                    help="only the FP32-vs-FP64 accuracy table, over STEPS steps (every 500), one JSON line")
     ap.add_argument("--layout-study", action="store_true",
                     help="per-kernel FP64 times on the 2160x8192 lattice for each layout (one JSON line)")
     args = ap.parse_args()
@@ -897,6 +953,10 @@ def main():
         out = [hetero_study(lx, ly) for lx, ly in sizes]
         print(json.dumps({"hetero": out}), flush=True)
         return
+    if args.fp32_accuracy:
+        every = 500 if args.fp32_accuracy <= 10000 else 2500
+        print(json.dumps({"fp32_accuracy": fp32_accuracy(args, nsteps=args.fp32_accuracy, every=every)}), flush=True)
+        return
     if args.layout_study:
         print(json.dumps({"layout_study": layout_study()}), flush=True)
         return
@@ -905,6 +965,8 @@ def main():
         res["fp32_accuracy_5000_steps"] = fp32_accuracy(args)
         res["adjoint_1024x2048_10000_steps"] = adjoint_at_scale()
         res["adjoint_1024x2048_10000_steps_lambda32"] = adjoint_at_scale(lam="fp32")
+        res["adjoint_512x512_2000_steps"] = adjoint_c4()
+        res["adjoint_512x512_2000_steps_lambda32"] = adjoint_c4(lam="fp32")
     res["cpu_baseline"] = None if args.skip_cpu else cpu_baseline(args)
     res["cpu_oracle_serial_256x128"] = None if args.skip_cpu else cpu_oracle_serial()
     print(json.dumps(res), flush=True)
