@@ -103,6 +103,7 @@ struct lbm_ctx {
     int wr_buf;
     WallTable wt;
     CollideArgs cargs;
+    unsigned fused_lds;  // dynamic LDS of the fused step's launch (occupancy cap; 0: none)
     std::string err;
 
     void* buf(int i) { return ws + pl.off_buf[i]; }
@@ -282,14 +283,15 @@ void launch_fused_kernel(lbm_ctx* c, const S* src, S* dst, const double* wr, dou
     const Geo& g = c->pl.geo;
     const bool walls = c->p.ybc == LBM_Y_WALLS;
     const bool wrap = c->p.xmode == LBM_X_WRAP;
+    const unsigned lds = sizeof(S) == 8 ? c->fused_lds : 0u;
     if (wrap && walls)
-        hipLaunchKernelGGL((k_step_fused<S, true, true, WIDE>), site_grid(g), dim3(SITE_THREADS), 0, c->stream, src, dst, g, c->cargs, wr, c->wt, wo);
+        hipLaunchKernelGGL((k_step_fused<S, true, true, WIDE>), site_grid(g), dim3(SITE_THREADS), lds, c->stream, src, dst, g, c->cargs, wr, c->wt, wo);
     else if (wrap)
-        hipLaunchKernelGGL((k_step_fused<S, true, false, WIDE>), site_grid(g), dim3(SITE_THREADS), 0, c->stream, src, dst, g, c->cargs, wr, c->wt, wo);
+        hipLaunchKernelGGL((k_step_fused<S, true, false, WIDE>), site_grid(g), dim3(SITE_THREADS), lds, c->stream, src, dst, g, c->cargs, wr, c->wt, wo);
     else if (walls)
-        hipLaunchKernelGGL((k_step_fused<S, false, true, WIDE>), site_grid(g), dim3(SITE_THREADS), 0, c->stream, src, dst, g, c->cargs, wr, c->wt, wo);
+        hipLaunchKernelGGL((k_step_fused<S, false, true, WIDE>), site_grid(g), dim3(SITE_THREADS), lds, c->stream, src, dst, g, c->cargs, wr, c->wt, wo);
     else
-        hipLaunchKernelGGL((k_step_fused<S, false, false, WIDE>), site_grid(g), dim3(SITE_THREADS), 0, c->stream, src, dst, g, c->cargs, wr, c->wt, wo);
+        hipLaunchKernelGGL((k_step_fused<S, false, false, WIDE>), site_grid(g), dim3(SITE_THREADS), lds, c->stream, src, dst, g, c->cargs, wr, c->wt, wo);
 }
 
 template <typename S>
@@ -546,6 +548,15 @@ lbm_status lbm_create(const lbm_params* p, void* dev_workspace, size_t bytes, vo
         c->wt.w[l] = W_SHELL[SHELL[l]];
     }
     set_collide_args(c);
+    // occupancy cap of the FP64 fused step on large lattices (lbm_kernels.hpp)
+    c->fused_lds = 0;
+    int dev = 0, ncu = 0, max_lds = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+        (size_t)max_lds >= FUSED_FP64_LDS_RESERVE && ncu > 0 &&
+        (size_t)site_grid(pl.geo).x >= (size_t)FUSED_FP64_CAP_MIN_BLOCKS_PER_CU * (size_t)ncu)
+        c->fused_lds = FUSED_FP64_LDS_RESERVE;
     if (hipMemsetAsync(dev_workspace, 0, pl.total, c->stream) != hipSuccess ||
         hipStreamSynchronize(c->stream) != hipSuccess) {
         g_create_error = "workspace initialisation failed";

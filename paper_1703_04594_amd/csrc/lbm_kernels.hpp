@@ -328,7 +328,19 @@ __global__ __launch_bounds__(SITE_THREADS) void k_collide(S* __restrict__ buf, G
 
 // ---------------------------------------------------------------------------
 // Fused step: gather (eq. (4) pull) + wall rule + collide, src -> dst.
+//
+// On large lattices the FP64 step is launched with FUSED_FP64_LDS_RESERVE
+// bytes of dynamic LDS that it does not use: that caps how many of its blocks
+// share a CU (2 rather than the 4 its registers allow), so fewer of its
+// 74-stream gather/store patterns are in flight at once.  Measured (HIP events,
+// median of five runs of 20 launches, two runs each): 2.5-3% faster from
+// 1024x2048 to 4096x4096 for any reserve from 56 to 72 KB; no change at
+// 1024x1024; 13% slower at 512x512, whose 1024 blocks no longer fit one
+// round.  The FP32 step and the other kernels measured slower capped.
 // ---------------------------------------------------------------------------
+constexpr unsigned FUSED_FP64_LDS_RESERVE = 64 * 1024;
+// the cap is applied from this many site blocks per CU on
+constexpr unsigned FUSED_FP64_CAP_MIN_BLOCKS_PER_CU = 16;
 template <typename S, bool WRAP, bool WALLS, bool WIDE = true>
 __global__ __launch_bounds__(SITE_THREADS) void k_step_fused(const S* __restrict__ src, S* __restrict__ dst, Geo g,
                                                           CollideArgs args, const double* __restrict__ wall_rho, WallTable wt,
