@@ -104,6 +104,7 @@ struct lbm_ctx {
     WallTable wt;
     CollideArgs cargs;
     unsigned fused_lds;  // dynamic LDS of the fused step's launch (occupancy cap; 0: none)
+    unsigned collide_lds;// the same for the split step's collide
     std::string err;
 
     void* buf(int i) { return ws + pl.off_buf[i]; }
@@ -252,12 +253,12 @@ void launch_collide(lbm_ctx* c, double* wo)
     const Geo& g = c->pl.geo;
     if constexpr (std::is_same<S, float>::value) {
         if (c->f32_sums()) {
-            hipLaunchKernelGGL((k_collide<S, WALLS, false>), site_grid(g), dim3(SITE_THREADS), 0, c->stream,
-                               (S*)c->buf(c->cur), g, c->cargs, wo);
+            hipLaunchKernelGGL((k_collide<S, WALLS, false>), site_grid(g), dim3(SITE_THREADS), c->collide_lds,
+                               c->stream, (S*)c->buf(c->cur), g, c->cargs, wo);
             return;
         }
     }
-    hipLaunchKernelGGL((k_collide<S, WALLS, true>), site_grid(g), dim3(SITE_THREADS), 0, c->stream,
+    hipLaunchKernelGGL((k_collide<S, WALLS, true>), site_grid(g), dim3(SITE_THREADS), c->collide_lds, c->stream,
                        (S*)c->buf(c->cur), g, c->cargs, wo);
 }
 
@@ -548,15 +549,19 @@ lbm_status lbm_create(const lbm_params* p, void* dev_workspace, size_t bytes, vo
         c->wt.w[l] = W_SHELL[SHELL[l]];
     }
     set_collide_args(c);
-    // occupancy cap of the FP64 fused step on large lattices (lbm_kernels.hpp)
+    // occupancy caps of the FP64 fused step and of the collide on large
+    // lattices (lbm_kernels.hpp)
     c->fused_lds = 0;
+    c->collide_lds = 0;
     int dev = 0, ncu = 0, max_lds = 0;
     if (hipGetDevice(&dev) == hipSuccess &&
         hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
-        hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
-        (size_t)max_lds >= FUSED_FP64_LDS_RESERVE && ncu > 0 &&
-        (size_t)site_grid(pl.geo).x >= (size_t)FUSED_FP64_CAP_MIN_BLOCKS_PER_CU * (size_t)ncu)
-        c->fused_lds = FUSED_FP64_LDS_RESERVE;
+        hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && ncu > 0 &&
+        (size_t)site_grid(pl.geo).x >= (size_t)FUSED_FP64_CAP_MIN_BLOCKS_PER_CU * (size_t)ncu) {
+        const unsigned coll = p->precision == LBM_FP64 ? COLLIDE_FP64_LDS_RESERVE : COLLIDE_FP32_LDS_RESERVE;
+        if ((size_t)max_lds >= FUSED_FP64_LDS_RESERVE) c->fused_lds = FUSED_FP64_LDS_RESERVE;
+        if ((size_t)max_lds >= coll) c->collide_lds = coll;
+    }
     if (hipMemsetAsync(dev_workspace, 0, pl.total, c->stream) != hipSuccess ||
         hipStreamSynchronize(c->stream) != hipSuccess) {
         g_create_error = "workspace initialisation failed";
