@@ -342,8 +342,10 @@ constexpr unsigned FUSED_FP64_LDS_RESERVE = 64 * 1024;
 // the cap is applied from this many site blocks per CU on
 constexpr unsigned FUSED_FP64_CAP_MIN_BLOCKS_PER_CU = 16;
 // The in-place collide of the split step takes the same kind of cap on large
-// lattices: 1 block per CU in FP64 (96 KB; 1.2-3% faster from 1024x1024 on)
-// and 2 in FP32 (64 KB; 1-5% faster from 1024x2048 on).
+// lattices in the columns layout: 1 block per CU in FP64 (96 KB; 1.2-3%
+// faster from 1024x1024 on) and 2 in FP32 (64 KB; 1-5% faster from 1024x2048
+// on).  In the planes layout the FP64 cap measured 2.5% slower, so that
+// layout keeps the full occupancy.
 constexpr unsigned COLLIDE_FP64_LDS_RESERVE = 96 * 1024;
 constexpr unsigned COLLIDE_FP32_LDS_RESERVE = 64 * 1024;
 template <typename S, bool WRAP, bool WALLS, bool WIDE = true>
