@@ -560,7 +560,8 @@ lbm_status lbm_create(const lbm_params* p, void* dev_workspace, size_t bytes, vo
         (size_t)site_grid(pl.geo).x >= (size_t)FUSED_FP64_CAP_MIN_BLOCKS_PER_CU * (size_t)ncu) {
         const unsigned coll = p->precision == LBM_FP64 ? COLLIDE_FP64_LDS_RESERVE : COLLIDE_FP32_LDS_RESERVE;
         if ((size_t)max_lds >= FUSED_FP64_LDS_RESERVE) c->fused_lds = FUSED_FP64_LDS_RESERVE;
-        if ((size_t)max_lds >= coll && p->layout == LBM_LAYOUT_COLUMNS) c->collide_lds = coll;
+        if ((size_t)max_lds >= coll && (p->precision != LBM_FP64 || p->layout == LBM_LAYOUT_COLUMNS))
+            c->collide_lds = coll;
     }
     if (hipMemsetAsync(dev_workspace, 0, pl.total, c->stream) != hipSuccess ||
         hipStreamSynchronize(c->stream) != hipSuccess) {

@@ -342,10 +342,13 @@ constexpr unsigned FUSED_FP64_LDS_RESERVE = 64 * 1024;
 // the cap is applied from this many site blocks per CU on
 constexpr unsigned FUSED_FP64_CAP_MIN_BLOCKS_PER_CU = 16;
 // The in-place collide of the split step takes the same kind of cap on large
-// lattices in the columns layout: 1 block per CU in FP64 (96 KB; 1.2-3%
-// faster from 1024x1024 on) and 2 in FP32 (64 KB; 1-5% faster from 1024x2048
-// on).  In the planes layout the FP64 cap measured 2.5% slower, so that
-// layout keeps the full occupancy.
+// lattices: 2 blocks per CU in FP32 (64 KB; 1-5% faster from 1024x2048 on, in
+// both layouts) and, in the columns layout, 1 block per CU in FP64 (96 KB;
+// 1.2-3% faster from 1024x1024 on).  In the planes layout the FP64 collide ran
+// 3% slower with 96 KB and unchanged with 64 KB, so it keeps full occupancy.
+// Its blocks keep the XCD renumbering although a collide shares no lines
+// between blocks: in hardware order the FP64 columns collide ran 14-18%
+// slower at 2048x4096 and 4096x4096.
 constexpr unsigned COLLIDE_FP64_LDS_RESERVE = 96 * 1024;
 constexpr unsigned COLLIDE_FP32_LDS_RESERVE = 64 * 1024;
 template <typename S, bool WRAP, bool WALLS, bool WIDE = true>
