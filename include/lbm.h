@@ -39,6 +39,10 @@
  *    without waiting.  Argument and state errors are reported at once; a
  *    failed launch returns LBM_ERR_HIP; faults of running kernels surface at
  *    lbm_sync or at a later call.  lbm_last_error gives the message.
+ *  - A context belongs to the device that is current at lbm_create (that of
+ *    its workspace and stream; its launch settings are chosen for that
+ *    device).  Every later call on the context is made with that device
+ *    current.
  *  - A context is used by one host thread at a time.  Two contexts may share
  *    nothing but the device.
  */
@@ -222,7 +226,8 @@ lbm_status lbm_loss_temperature(lbm_ctx* ctx, const double* T_target, double* de
  * seed for an arbitrary upstream gradient dT of the temperature field. */
 lbm_status lbm_adjoint_seed_temperature(lbm_ctx* ctx, const double* dT);
 /* One reverse step: with f_n (a device state snapshot, lbm_state_bytes,
- * as written by lbm_get_state after n forward steps) and lambda_{n+1} in the
+ * 256-byte aligned, as written by lbm_get_state or lbm_step_state after n
+ * forward steps of a context with the same parameters) and lambda_{n+1} in the
  * context, replaces lambda by lambda_n = (d step / d f_n)^T lambda_{n+1}
  * (collide^T, bc^T and propagate^T) and adds lambda_{n+1} . d step/d tau to
  * *dev_dtau_acc (device FP64 scalar).  The snapshot is only read; the
@@ -230,6 +235,8 @@ lbm_status lbm_adjoint_seed_temperature(lbm_ctx* ctx, const double* dT);
  * step's collide^T output and applies bc^T and propagate^T when lambda_n is
  * next read (by the next reverse step, lbm_adjoint_init_rt or
  * lbm_adjoint_get_lambda), so those reads see lambda_n exactly. */
+/* Errors: LBM_ERR_STATE without adjoint buffers or before lambda is seeded,
+ * LBM_ERR_INVALID for a NULL or misaligned pointer. */
 lbm_status lbm_adjoint_step(lbm_ctx* ctx, const void* f_n_state, double* dev_dtau_acc);
 /* dP <- dL/dP for the initial state of lbm_init_rt(P, prof), from lambda_0. */
 lbm_status lbm_adjoint_init_rt(lbm_ctx* ctx, const double* P,

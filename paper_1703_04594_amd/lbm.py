@@ -205,11 +205,11 @@ class Lattice:
         with torch.cuda.device(self.device):
             self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
             self.stream = torch.cuda.current_stream(self.device)
-        base = self.workspace.data_ptr()
-        self._ws_ptr = (base + 255) // 256 * 256
-        h = ctypes.c_void_p()
-        st = self.L.lbm_create(ctypes.byref(self.p), ctypes.c_void_p(self._ws_ptr), nbytes,
-                               ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+            base = self.workspace.data_ptr()
+            self._ws_ptr = (base + 255) // 256 * 256
+            h = ctypes.c_void_p()
+            st = self.L.lbm_create(ctypes.byref(self.p), ctypes.c_void_p(self._ws_ptr), nbytes,
+                                   ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
         if st != 0:
             raise LBMError(f"lbm_create: {self.L.lbm_last_error(None).decode()} (status {st})")
         self.h = h
@@ -218,6 +218,16 @@ class Lattice:
     def _check(self, st: int, what: str):
         if st != 0:
             raise LBMError(f"{what}: {self.L.lbm_last_error(self.h).decode()} (status {st})")
+
+    def _run(self, what: str, fn, *args):
+        """fn(context, *args) with the lattice's device current (the C ABI's
+        convention), then the status check."""
+        if torch.cuda.current_device() == self.device.index:
+            st = fn(self.h, *args)
+        else:
+            with torch.cuda.device(self.device):
+                st = fn(self.h, *args)
+        self._check(st, what)
 
     def close(self):
         if getattr(self, "h", None):
@@ -238,41 +248,42 @@ class Lattice:
 
     # ------------------------------------------------------------------
     def set_tau(self, tau: float):
-        self._check(self.L.lbm_set_tau(self.h, tau), "set_tau")
+        self._run("set_tau", self.L.lbm_set_tau, tau)
 
     def init(self, rho, ux, uy, T):
-        self._check(self.L.lbm_init(self.h, self._field(rho), self._field(ux), self._field(uy),
-                                    self._field(T)), "init")
+        self._run("init", self.L.lbm_init, self._field(rho), self._field(ux), self._field(uy), self._field(T))
 
     def init_rt(self, P, profile: RtProfile | None = None):
         prof = (profile or RtProfile()).c(self.ly)
-        self._check(self.L.lbm_init_rt(self.h, self._field(P), ctypes.byref(prof)), "init_rt")
+        self._run("init_rt", self.L.lbm_init_rt, self._field(P), ctypes.byref(prof))
 
     def propagate(self):
-        self._check(self.L.lbm_propagate(self.h), "propagate")
+        self._run("propagate", self.L.lbm_propagate)
 
     def bc(self):
-        self._check(self.L.lbm_bc(self.h), "bc")
+        self._run("bc", self.L.lbm_bc)
 
     def collide(self):
-        self._check(self.L.lbm_collide(self.h), "collide")
+        self._run("collide", self.L.lbm_collide)
 
     def step(self, n: int = 1):
-        self._check(self.L.lbm_step(self.h, int(n)), "step")
+        self._run("step", self.L.lbm_step, int(n))
 
     def macros(self):
         out = [self._new_field() for _ in range(4)]
-        self._check(self.L.lbm_get_macros(self.h, *[ctypes.c_void_p(t.data_ptr()) for t in out]), "get_macros")
+        self._run("get_macros", self.L.lbm_get_macros, *[ctypes.c_void_p(t.data_ptr()) for t in out])
         return tuple(out)
 
     def get_pops(self) -> torch.Tensor:
+        """Canonical (37, lx, ly) populations: float64 f for "fp64", float32
+        deviations f - w for the FP32 forms (set_pops takes the same)."""
         out = torch.empty((NPOP, self.lx, self.ly), dtype=self.store_dtype, device=self.device)
-        self._check(self.L.lbm_get_pops(self.h, ctypes.c_void_p(out.data_ptr())), "get_pops")
+        self._run("get_pops", self.L.lbm_get_pops, ctypes.c_void_p(out.data_ptr()))
         return out
 
     def set_pops(self, f: torch.Tensor):
         p = _ptr(f, self.store_dtype, (NPOP, self.lx, self.ly), self.device)
-        self._check(self.L.lbm_set_pops(self.h, ctypes.c_void_p(p)), "set_pops")
+        self._run("set_pops", self.L.lbm_set_pops, ctypes.c_void_p(p))
 
     def new_state(self) -> torch.Tensor:
         return torch.empty(self.state_bytes, dtype=torch.uint8, device=self.device)
@@ -280,58 +291,58 @@ class Lattice:
     def get_state(self, out: torch.Tensor | None = None) -> torch.Tensor:
         out = self.new_state() if out is None else out
         p = _ptr(out, torch.uint8, (self.state_bytes,), self.device)
-        self._check(self.L.lbm_get_state(self.h, ctypes.c_void_p(p)), "get_state")
+        self._run("get_state", self.L.lbm_get_state, ctypes.c_void_p(p))
         return out
 
     def set_state(self, s: torch.Tensor):
         p = _ptr(s, torch.uint8, (self.state_bytes,), self.device)
-        self._check(self.L.lbm_set_state(self.h, ctypes.c_void_p(p)), "set_state")
+        self._run("set_state", self.L.lbm_set_state, ctypes.c_void_p(p))
 
     def step_state(self, src: torch.Tensor, dst: torch.Tensor):
         """dst <- one step from the snapshot src (lbm_step_state); the
         lattice's own state is untouched."""
         ps = _ptr(src, torch.uint8, (self.state_bytes,), self.device)
         pd = _ptr(dst, torch.uint8, (self.state_bytes,), self.device)
-        self._check(self.L.lbm_step_state(self.h, ctypes.c_void_p(ps), ctypes.c_void_p(pd)), "step_state")
+        self._run("step_state", self.L.lbm_step_state, ctypes.c_void_p(ps), ctypes.c_void_p(pd))
 
     def conservation(self) -> torch.Tensor:
         out = torch.empty(4, dtype=torch.float64, device=self.device)
-        self._check(self.L.lbm_conservation(self.h, ctypes.c_void_p(out.data_ptr())), "conservation")
+        self._run("conservation", self.L.lbm_conservation, ctypes.c_void_p(out.data_ptr()))
         return out
 
     # -- adjoint ----------------------------------------------------------
     def loss_temperature(self, T_target) -> torch.Tensor:
         out = torch.empty((), dtype=torch.float64, device=self.device)
-        self._check(self.L.lbm_loss_temperature(self.h, self._field(T_target), ctypes.c_void_p(out.data_ptr())),
-                    "loss_temperature")
+        self._run("loss_temperature", self.L.lbm_loss_temperature, self._field(T_target),
+                  ctypes.c_void_p(out.data_ptr()))
         return out
 
     def seed_temperature(self, dT):
-        self._check(self.L.lbm_adjoint_seed_temperature(self.h, self._field(dT)), "seed_temperature")
+        self._run("seed_temperature", self.L.lbm_adjoint_seed_temperature, self._field(dT))
 
     def adjoint_step(self, state: torch.Tensor, dtau_acc: torch.Tensor):
         p = _ptr(state, torch.uint8, (self.state_bytes,), self.device)
         a = _ptr(dtau_acc, torch.float64, (), self.device)
-        self._check(self.L.lbm_adjoint_step(self.h, ctypes.c_void_p(p), ctypes.c_void_p(a)), "adjoint_step")
+        self._run("adjoint_step", self.L.lbm_adjoint_step, ctypes.c_void_p(p), ctypes.c_void_p(a))
 
     def adjoint_init_rt(self, P, profile: RtProfile | None = None) -> torch.Tensor:
         prof = (profile or RtProfile()).c(self.ly)
         out = self._new_field()
-        self._check(self.L.lbm_adjoint_init_rt(self.h, self._field(P), ctypes.byref(prof),
-                                               ctypes.c_void_p(out.data_ptr())), "adjoint_init_rt")
+        self._run("adjoint_init_rt", self.L.lbm_adjoint_init_rt, self._field(P), ctypes.byref(prof),
+                  ctypes.c_void_p(out.data_ptr()))
         return out
 
     def get_lambda(self) -> torch.Tensor:
         out = torch.empty((NPOP, self.lx, self.ly), dtype=torch.float64, device=self.device)
-        self._check(self.L.lbm_adjoint_get_lambda(self.h, ctypes.c_void_p(out.data_ptr())), "get_lambda")
+        self._run("get_lambda", self.L.lbm_adjoint_get_lambda, ctypes.c_void_p(out.data_ptr()))
         return out
 
     def set_lambda(self, lam: torch.Tensor):
         p = _ptr(lam, torch.float64, (NPOP, self.lx, self.ly), self.device)
-        self._check(self.L.lbm_adjoint_set_lambda(self.h, ctypes.c_void_p(p)), "set_lambda")
+        self._run("set_lambda", self.L.lbm_adjoint_set_lambda, ctypes.c_void_p(p))
 
     def sync(self):
-        self._check(self.L.lbm_sync(self.h), "sync")
+        self._run("sync", self.L.lbm_sync)
 
 
 def conservation_noalloc(pops: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
@@ -502,10 +513,10 @@ class Hetero:
         with torch.cuda.device(self.device):
             self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
             self.stream = torch.cuda.current_stream(self.device)
-        ws = (self.workspace.data_ptr() + 255) // 256 * 256
-        h = ctypes.c_void_p()
-        st = self.L.lbm_hetero_create(ctypes.byref(self.p), self.m, int(host_threads), ctypes.c_void_p(ws), nbytes,
-                                      ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+            ws = (self.workspace.data_ptr() + 255) // 256 * 256
+            h = ctypes.c_void_p()
+            st = self.L.lbm_hetero_create(ctypes.byref(self.p), self.m, int(host_threads), ctypes.c_void_p(ws),
+                                          nbytes, ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
         if st != 0:
             raise LBMError(f"lbm_hetero_create: {self.L.lbm_hetero_last_error(None).decode()} (status {st})")
         self.h = h
@@ -513,6 +524,11 @@ class Hetero:
     def _check(self, st, what):
         if st != 0:
             raise LBMError(f"{what}: {self.L.lbm_hetero_last_error(self.h).decode()} (status {st})")
+
+    def _run(self, what: str, fn, *args):
+        with torch.cuda.device(self.device):
+            st = fn(self.h, *args)
+        self._check(st, what)
 
     def close(self):
         if getattr(self, "h", None):
@@ -527,18 +543,18 @@ class Hetero:
 
     def set_pops(self, canon):
         c = _host_canon(canon, self.lx, self.ly)
-        self._check(self.L.lbm_hetero_set_pops(self.h, _dp(c)), "hetero_set_pops")
+        self._run("hetero_set_pops", self.L.lbm_hetero_set_pops, _dp(c))
 
     def get_pops(self) -> _np.ndarray:
         out = _np.empty((NPOP, self.lx, self.ly))
-        self._check(self.L.lbm_hetero_get_pops(self.h, _dp(out)), "hetero_get_pops")
+        self._run("hetero_get_pops", self.L.lbm_hetero_get_pops, _dp(out))
         return out
 
     def step(self, n: int = 1):
-        self._check(self.L.lbm_hetero_step(self.h, int(n)), "hetero_step")
+        self._run("hetero_step", self.L.lbm_hetero_step, int(n))
 
     def times(self) -> dict:
         """Per-step averages of the last step() call, seconds."""
         t = (ctypes.c_double * 4)()
-        self._check(self.L.lbm_hetero_times(self.h, t), "hetero_times")
+        self._run("hetero_times", self.L.lbm_hetero_times, t)
         return {"wall": t[0], "host": t[1], "gpu": t[2], "swap": t[3]}

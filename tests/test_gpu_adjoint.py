@@ -393,3 +393,31 @@ def test_reverse_step_over_f32sums_states_equals_fp32():
         lat.adjoint_step(st, dacc)
         out.append((lat.get_lambda(), dacc))
     assert torch.equal(out[0][0], out[1][0]) and torch.equal(out[0][1], out[1][1])
+
+
+def test_adjoint_step_rejects_bad_calls_before_launching():
+    """lbm_adjoint_step's host checks: no seed yet (state error), a
+    misaligned snapshot, a context without adjoint buffers; nothing is
+    launched, and a valid call afterwards still works."""
+    from paper_1703_04594_amd.lbm import LBMError
+    lx, ly = 24, 20
+    say("adjoint_step host checks")
+    lat = Lattice(lx, ly, TAU, -1e-3, TB, TT, adjoint=True, device=DEV)
+    lat.set_pops((WT[:, None, None] * torch.ones(lx, ly, dtype=torch.float64)).to(DEV))
+    st = lat.get_state()
+    dacc = torch.zeros((), dtype=torch.float64, device=DEV)
+    with pytest.raises(LBMError, match="not seeded"):
+        lat.adjoint_step(st, dacc)
+    lat.set_lambda(torch.tensor(inputs.population_noise(lx, ly, 91)).to(DEV))
+    raw = torch.empty(lat.state_bytes + 256, dtype=torch.uint8, device=DEV)
+    off = (-raw.data_ptr()) % 256 + 8
+    bad = raw[off:off + lat.state_bytes]
+    bad.copy_(st)
+    with pytest.raises(LBMError, match="aligned"):
+        lat.adjoint_step(bad, dacc)
+    lat.adjoint_step(st, dacc)
+    lat.sync()
+    assert torch.isfinite(dacc).item() and torch.isfinite(lat.get_lambda()).all().item()
+    plain = Lattice(lx, ly, TAU, device=DEV)
+    with pytest.raises(LBMError, match="adjoint buffers"):
+        plain.adjoint_step(plain.get_state(), dacc)

@@ -404,6 +404,35 @@ def test_full_size_2048x4096_sampled_parity(step):
         assert err <= 1e-12, (x0, y0, err)
 
 
+@pytest.mark.parametrize("precision,step,layout", [
+    ("fp64", "split", "columns"), ("fp64", "fused", "columns"), ("fp64", "fused", "planes"),
+    ("fp32", "split", "columns"), ("fp32", "split", "planes"), ("fp32_f32sums", "split", "columns")])
+def test_occupancy_capped_launches_sampled_parity(precision, step, layout):
+    """1024x1024 has 4096 site blocks, 16 per CU of a 256-CU GPU: the size
+    from which the fused FP64 step and the split step's collide are launched
+    with an LDS reserve that lowers their occupancy.  20 steps of the RT run,
+    then sampled sites against windowed oracle runs: FP64 per population
+    relative to its weight <= 1e-12; the FP32 forms <= 1e-5 (FP32 rounding of
+    the stored deviations, ~6e-8 of their size per step; the FP32 forms store
+    f - w, widened here before the comparison)."""
+    lx, ly, n = 1024, 1024, 20
+    say(f"capped launches {precision} {step} {layout}")
+    P = inputs.rt_perturbation(lx, ly, 5)
+    lat = Lattice(lx, ly, TAU, G, TB, TT, precision=precision, step=step, layout=layout, device=DEV)
+    lat.init_rt(tg(P))
+    lat.step(n)
+    f = lat.get_pops()
+    bar = 1e-12 if precision == "fp64" else 1e-5
+    for (x0, y0) in [(0, 0), (1023, 1023), (511, 1), (700, 512), (3, 1021), (256, 300)]:
+        got = f[:, x0, y0].double().cpu().numpy()
+        if precision != "fp64":
+            got = got + W             # FP32 forms store f - w
+        want = oracle_window_site(P, lx, ly, x0, y0, n)
+        err = float(np.max(np.abs(got - want) / W))
+        say(f"  site ({x0},{y0}) err {err:.2e}")
+        assert err <= bar, (x0, y0, err)
+
+
 @pytest.mark.parametrize("ybc,xmode", [("walls", "wrap"), ("periodic", "wrap"), ("walls", "halo")])
 def test_fp32_conservation_matches_oracle_of_the_widened_state(ybc, xmode):
     """lbm_conservation on FP32-shifted storage (the FP64 reduction the
