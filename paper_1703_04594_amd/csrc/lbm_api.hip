@@ -105,6 +105,7 @@ struct lbm_ctx {
     CollideArgs cargs;
     unsigned fused_lds;  // dynamic LDS of the fused step's launch (occupancy cap; 0: none)
     unsigned collide_lds;// the same for the split step's collide
+    unsigned adj_lds;    // the same for the reverse step
     std::string err;
 
     void* buf(int i) { return ws + pl.off_buf[i]; }
@@ -513,6 +514,30 @@ lbm_status launch_conservation_noalloc(const Geo& g, const void* pops, double* p
 
 }  // namespace
 
+namespace {
+
+// Blocks of the reverse step's kernel that fit one CU at full occupancy
+// (0 if the runtime cannot tell).
+template <typename S, typename L>
+int adj_blocks_per_cu_t()
+{
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_adj_collide<S, L, true, true>, SITE_THREADS, 0) !=
+        hipSuccess)
+        return 0;
+    return n;
+}
+
+int adj_blocks_per_cu(const lbm_params* p)
+{
+    const bool lam32 = p->adjoint == 2;
+    if (p->precision == LBM_FP64)
+        return lam32 ? adj_blocks_per_cu_t<double, float>() : adj_blocks_per_cu_t<double, double>();
+    return lam32 ? adj_blocks_per_cu_t<float, float>() : adj_blocks_per_cu_t<float, double>();
+}
+
+}  // namespace
+
 // ============================================================================
 // C ABI
 // ============================================================================
@@ -562,6 +587,14 @@ lbm_status lbm_create(const lbm_params* p, void* dev_workspace, size_t bytes, vo
         if ((size_t)max_lds >= FUSED_FP64_LDS_RESERVE) c->fused_lds = FUSED_FP64_LDS_RESERVE;
         if ((size_t)max_lds >= coll && (p->precision != LBM_FP64 || p->layout == LBM_LAYOUT_COLUMNS))
             c->collide_lds = coll;
+    }
+    c->adj_lds = 0;
+    if (p->adjoint && ncu > 0 && (size_t)max_lds >= ADJ_LDS_RESERVE) {
+        const int full = adj_blocks_per_cu(p);
+        const size_t nb = site_grid(pl.geo).x;
+        auto rounds = [&](int per_cu) { return (nb + (size_t)per_cu * ncu - 1) / ((size_t)per_cu * ncu); };
+        if (full > ADJ_CAP_BLOCKS_PER_CU && rounds(ADJ_CAP_BLOCKS_PER_CU) <= rounds(full))
+            c->adj_lds = ADJ_LDS_RESERVE;
     }
     if (hipMemsetAsync(dev_workspace, 0, pl.total, c->stream) != hipSuccess ||
         hipStreamSynchronize(c->stream) != hipSuccess) {

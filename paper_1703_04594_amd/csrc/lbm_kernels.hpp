@@ -351,6 +351,14 @@ constexpr unsigned FUSED_FP64_CAP_MIN_BLOCKS_PER_CU = 16;
 // slower at 2048x4096 and 4096x4096.
 constexpr unsigned COLLIDE_FP64_LDS_RESERVE = 96 * 1024;
 constexpr unsigned COLLIDE_FP32_LDS_RESERVE = 64 * 1024;
+// The reverse step (k_adj_collide, 3 blocks per CU by its registers) takes a
+// reserve that leaves 2 blocks per CU only when that does not add a round of
+// blocks: rounds = ceil(blocks / (blocks per CU x CUs)).  That holds on small
+// lattices alone (up to 4 blocks per CU), e.g. 512x512, where it runs 12%
+// (FP64 lambda) and 2% (FP32 lambda) faster; wherever the cap adds a round it
+// cost 3-60% (sweep from 256x256 to 2048x4096).
+constexpr unsigned ADJ_LDS_RESERVE = 64 * 1024;
+constexpr int ADJ_CAP_BLOCKS_PER_CU = 2;
 template <typename S, bool WRAP, bool WALLS, bool WIDE = true>
 __global__ __launch_bounds__(SITE_THREADS) void k_step_fused(const S* __restrict__ src, S* __restrict__ dst, Geo g,
                                                           CollideArgs args, const double* __restrict__ wall_rho, WallTable wt,
