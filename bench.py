@@ -300,9 +300,9 @@ def run(args):
         lat.step(10)
         st = lat.get_state()
         lat.step(1)
-        dacc = torch.zeros((), dtype=torch.float64, device=dev)
         lat.seed_temperature(torch.ones((lx, ly), dtype=torch.float64, device=dev))
-        t_adj[lam] = float(np.median([time_launches(lambda: lat.adjoint_step(st, dacc), s, 10) for _ in range(5)]))
+        # as the rollout runs it: d/dtau kept per block, one reduction per sweep
+        t_adj[lam] = float(np.median([time_launches(lambda: lat.adjoint_step(st, None), s, 10) for _ in range(5)]))
         t_fwd32 = float(np.median([time_launches(lambda: lat.step(1), s, 10) for _ in range(5)]))
         del lat, st
         torch.cuda.empty_cache()
@@ -479,8 +479,7 @@ def adjoint_at_scale(lx=1024, ly=2048, nsteps=10000, budget=32 * 10 ** 9, lam="f
     st = probe.get_state()
     probe.step(1)
     probe.seed_temperature(torch.ones((lx, ly), dtype=torch.float64, device=dev))
-    dacc = torch.zeros((), dtype=torch.float64, device=dev)
-    t_adj = time_launches(lambda: probe.adjoint_step(st, dacc), probe.stream, 20)
+    t_adj = time_launches(lambda: probe.adjoint_step(st, None), probe.stream, 20)
     t_step = time_launches(lambda: probe.step(1), probe.stream, 20)
     state_bytes = probe.state_bytes
     del probe, st
@@ -549,8 +548,7 @@ def adjoint_c4(lx=512, ly=512, nsteps=2000, lam="fp64"):
     st = probe.get_state()
     probe.step(1)
     probe.seed_temperature(torch.ones((lx, ly), dtype=torch.float64, device=dev))
-    dacc = torch.zeros((), dtype=torch.float64, device=dev)
-    t_adj = float(np.median([time_launches(lambda: probe.adjoint_step(st, dacc), probe.stream, 50) for _ in range(5)]))
+    t_adj = float(np.median([time_launches(lambda: probe.adjoint_step(st, None), probe.stream, 50) for _ in range(5)]))
     t_step = float(np.median([time_launches(lambda: probe.step(1), probe.stream, 50) for _ in range(5)]))
     del probe, st
     cfg = RolloutConfig(lx, ly, nsteps, precision="fp32", checkpoint="sqrt", lambda_precision=lam)
@@ -807,7 +805,8 @@ def profile_workload(args):
         lat.seed_temperature(torch.ones((lx, ly), dtype=torch.float64, device=dev))
         dacc = torch.zeros((), dtype=torch.float64, device=dev)
         for _ in range(args.steps):
-            lat.adjoint_step(st, dacc)
+            lat.adjoint_step(st, None)
+        lat.take_dtau(dacc)
         torch.cuda.synchronize()
         del lat, st
     lat = Lattice(lx, ly, 0.7, -1e-5, 4 / 3, 2 / 3, precision="fp32_f32sums", step="fused", device=dev)

@@ -215,9 +215,10 @@ lbm_status lbm_conservation_noalloc(int precision, int lx, int ly, const void* p
 
 /* ---- adjoint (requires params.adjoint != 0) ------------------------------- */
 /* The adjoint state lambda = dL/df (one value per population and site; stored
- * in FP64, or FP32 when params.adjoint == 2) lives in the workspace.  A reverse sweep is: seed lambda_N, then for
- * n = N-1 .. 0 call lbm_adjoint_step with the forward state f_n, then
- * lbm_adjoint_init_rt for dL/dP. */
+ * in FP64, or FP32 when params.adjoint == 2) lives in the workspace.  A
+ * reverse sweep is: seed lambda_N, then for n = N-1 .. 0 call
+ * lbm_adjoint_step with the forward state f_n, then lbm_adjoint_init_rt for
+ * dL/dP (and lbm_adjoint_take_dtau for dL/dtau if the steps deferred it). */
 
 /* lambda <- dL/df of L = 1/2 sum (T - T_target)^2 at the current state;
  * *dev_loss (device FP64 scalar) <- L.  T_target: device FP64 [lx][ly]. */
@@ -234,10 +235,19 @@ lbm_status lbm_adjoint_seed_temperature(lbm_ctx* ctx, const double* dT);
  * population buffers are not touched.  Internally the context keeps the
  * step's collide^T output and applies bc^T and propagate^T when lambda_n is
  * next read (by the next reverse step, lbm_adjoint_init_rt or
- * lbm_adjoint_get_lambda), so those reads see lambda_n exactly. */
+ * lbm_adjoint_get_lambda), so those reads see lambda_n exactly.
+ * dev_dtau_acc may be NULL: the step's d/dtau term is then added to sums the
+ * context keeps per block of sites (no reduction kernel for this step), and
+ * lbm_adjoint_take_dtau later adds all such terms to a scalar at once. */
 /* Errors: LBM_ERR_STATE without adjoint buffers or before lambda is seeded,
- * LBM_ERR_INVALID for a NULL or misaligned pointer. */
+ * LBM_ERR_INVALID for a NULL or misaligned snapshot. */
 lbm_status lbm_adjoint_step(lbm_ctx* ctx, const void* f_n_state, double* dev_dtau_acc);
+/* *dev_dtau_acc (device FP64 scalar) += the d/dtau terms of every
+ * lbm_adjoint_step called with a NULL accumulator since the context was
+ * created or last taken from, then those sums restart at zero.  Summed per
+ * block over steps, then over blocks, in a fixed order: reproducible, and
+ * equal to per-step accumulation up to rounding. */
+lbm_status lbm_adjoint_take_dtau(lbm_ctx* ctx, double* dev_dtau_acc);
 /* dP <- dL/dP for the initial state of lbm_init_rt(P, prof), from lambda_0. */
 lbm_status lbm_adjoint_init_rt(lbm_ctx* ctx, const double* P,
                                const lbm_rt_profile* prof, double* dP);

@@ -229,7 +229,8 @@ class Executor:
     into the target slot (Lattice.step_state), so a replayed segment goes
     from snapshot to snapshot without copying states in or out of the
     lattice.  Results are bitwise those of the plain sequence (set_state,
-    step, get_state)."""
+    step, get_state).  Reverse steps keep their d/dtau terms in the lattice
+    (no reduction per step); run() adds them to dtau_acc before it returns."""
 
     LATTICE = -1
 
@@ -237,6 +238,7 @@ class Executor:
         self.lat = lat
         self.dtau = dtau_acc
         self.chain = chain
+        self.pending_dtau = False
         self.slots: dict[int, object] = {}
         self.where = Executor.LATTICE
         self.forward_steps = 0
@@ -290,10 +292,15 @@ class Executor:
                     self.state_copies += 1
                     self.where = Executor.LATTICE
             elif op == "adjoint":
-                self.lat.adjoint_step(self.slots[act[2]], self.dtau)
+                # d/dtau terms kept in the lattice, added to self.dtau at the end
+                self.lat.adjoint_step(self.slots[act[2]], None)
                 self.adjoint_steps += 1
+                self.pending_dtau = True
             elif op == "free":
                 pass   # slots are kept allocated and reused by index
             else:
                 raise ValueError(op)
             i += 1
+        if self.pending_dtau:
+            self.lat.take_dtau(self.dtau)
+            self.pending_dtau = False

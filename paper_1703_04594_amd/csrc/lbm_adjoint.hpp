@@ -161,10 +161,10 @@ __host__ __device__ __forceinline__ double adjoint_site(double m0, double sx, do
 }
 
 // One block sum of a double into partials[blockIdx linear].
-__device__ __forceinline__ void block_sum1(double v, double* __restrict__ partials)
+__device__ __forceinline__ void block_sum1(double v, double* __restrict__ partials, bool add = false)
 {
     double a[1] = {v};
-    block_sum_store<1, SITE_THREADS>(a, partials + (size_t)blockIdx.y * gridDim.x + blockIdx.x);
+    block_sum_store<1, SITE_THREADS>(a, partials + (size_t)blockIdx.y * gridDim.x + blockIdx.x, add);
 }
 
 // lambda_{n+1} at site (x, y) (see the header): from a buffer that holds mu
@@ -220,11 +220,12 @@ __device__ __forceinline__ void load_lambda(const L* __restrict__ buf, const Geo
 
 // One reverse step at site (x, y): lambda_{n+1} (load_lambda), the gather
 // g = bc(propagate(f_n)) of the snapshot f_n, collide^T, and mu stored at the
-// site (aligned, non-temporal); the d/dtau term goes to partials.
+// site (aligned, non-temporal); the block's d/dtau term goes to its slot of
+// partials (add: added to the slot, which then sums the terms of many steps).
 template <typename S, typename L, bool WALLS, bool GATHER>
 __global__ __launch_bounds__(SITE_THREADS) void k_adj_collide(
     const S* __restrict__ fn, Geo g, const L* __restrict__ lam_in, L* __restrict__ mu_out, Geo lg,
-    AdjArgs a, const double* __restrict__ wall_rho, WallTable wt, double* __restrict__ partials)
+    AdjArgs a, const double* __restrict__ wall_rho, WallTable wt, double* __restrict__ partials, int add)
 {
     const SiteBlock sb = site_block(g);
     const int x = sb.x, y = sb.y;
@@ -285,7 +286,7 @@ __global__ __launch_bounds__(SITE_THREADS) void k_adj_collide(
 #pragma unroll
         for (int l = 0; l < NPOP; ++l) st_nt(mcol + (size_t)l * lg.ps, yd, (L)lam[l]);
     }
-    block_sum1(dtau, partials);
+    block_sum1(dtau, partials, add != 0);
 }
 
 // lambda_l = d(x,y) dT/df_l = d (|xi_l - u|^2 - 2T) / (2 rho), with

@@ -34,6 +34,7 @@ struct Plan {
     size_t off_part;  // RED_BLOCKS * 4 doubles, then 2 doubles of loss/dtau scratch
     size_t off_lam[2];
     size_t off_apart; // adjoint: one double per collide block
+    size_t off_adacc; // adjoint: per-block sums of deferred d/dtau terms
     size_t total;
 };
 
@@ -75,6 +76,7 @@ Plan plan(const lbm_params* p)
         pl.off_lam[1] = off; off += lb;
         const size_t nb = (size_t)((p->ly + SITE_THREADS - 1) / SITE_THREADS) * p->lx;
         pl.off_apart = off; off += align_up(nb * 8, ALIGN);
+        pl.off_adacc = off; off += align_up(nb * 8, ALIGN);
     }
     pl.total = off;
     return pl;
@@ -436,7 +438,7 @@ lbm_status do_conservation(lbm_ctx* c, double* out4)
     lbm_status s = check_launch(c, "conservation");
     if (s) return s;
     hipLaunchKernelGGL((k_reduce_partials<4, false>), dim3(1), dim3(REDUCE_THREADS), 0, c->stream,
-                       (const double*)c->partials(), RED_BLOCKS, out4);
+                       c->partials(), RED_BLOCKS, out4);
     return check_launch(c, "conservation reduce");
 }
 }  // namespace
@@ -502,7 +504,7 @@ lbm_status launch_conservation_noalloc(const Geo& g, const void* pops, double* p
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) {
         hipLaunchKernelGGL((k_reduce_partials<4, false>), dim3(1), dim3(REDUCE_THREADS), 0, st,
-                           (const double*)part, RED_BLOCKS, out4);
+                           part, RED_BLOCKS, out4);
         e = hipGetLastError();
     }
     if (e != hipSuccess) {

@@ -501,8 +501,9 @@ __device__ __forceinline__ double wave_sum(double v)
 }
 
 // Sum of v over a block of NT threads (NT a multiple of 64), written to out.
+// Block sum of N values per thread into out[0..N) (add: out[k] += sum).
 template <int N, int NT>
-__device__ __forceinline__ void block_sum_store(double (&v)[N], double* __restrict__ out)
+__device__ __forceinline__ void block_sum_store(double (&v)[N], double* __restrict__ out, bool add = false)
 {
     static_assert(NT % 64 == 0, "whole wavefronts");
     __shared__ double red[N][NT / 64];
@@ -516,7 +517,7 @@ __device__ __forceinline__ void block_sum_store(double (&v)[N], double* __restri
     if (threadIdx.x < N) {
         double s = 0.0;
         for (int w = 0; w < NT / 64; ++w) s += red[threadIdx.x][w];
-        out[threadIdx.x] = s;
+        out[threadIdx.x] = add ? out[threadIdx.x] + s : s;
     }
 }
 
@@ -546,11 +547,12 @@ __global__ __launch_bounds__(256) void k_conservation_partial(const S* __restric
 // out[k] (+)= sum over nparts of partials[p * N + k]: one block of
 // REDUCE_THREADS threads, each with 4 interleaved accumulators, then a fixed
 // wave/LDS tree.  The order depends only on nparts, so results are bitwise
-// reproducible.
+// reproducible.  CLEAR: each thread zeroes the partials it read.
 constexpr int REDUCE_THREADS = 1024;
 
-template <int N, bool ACCUMULATE>
-__global__ __launch_bounds__(REDUCE_THREADS) void k_reduce_partials(const double* __restrict__ partials, int nparts, double* __restrict__ out)
+template <int N, bool ACCUMULATE, bool CLEAR = false>
+__global__ __launch_bounds__(REDUCE_THREADS) void k_reduce_partials(double* __restrict__ partials, int nparts,
+                                                                    double* __restrict__ out)
 {
     double acc[4][N];
 #pragma unroll
@@ -562,11 +564,19 @@ __global__ __launch_bounds__(REDUCE_THREADS) void k_reduce_partials(const double
 #pragma unroll
         for (int j = 0; j < 4; ++j)
 #pragma unroll
-            for (int k = 0; k < N; ++k) acc[j][k] += partials[(size_t)(p + j * REDUCE_THREADS) * N + k];
+            for (int k = 0; k < N; ++k) {
+                double* q = partials + (size_t)(p + j * REDUCE_THREADS) * N + k;
+                acc[j][k] += *q;
+                if (CLEAR) *q = 0.0;
+            }
     }
     for (int j = 0; p + j * REDUCE_THREADS < nparts; ++j)
 #pragma unroll
-        for (int k = 0; k < N; ++k) acc[j][k] += partials[(size_t)(p + j * REDUCE_THREADS) * N + k];
+        for (int k = 0; k < N; ++k) {
+            double* q = partials + (size_t)(p + j * REDUCE_THREADS) * N + k;
+            acc[j][k] += *q;
+            if (CLEAR) *q = 0.0;
+        }
     double v[N];
 #pragma unroll
     for (int k = 0; k < N; ++k) v[k] = (acc[0][k] + acc[1][k]) + (acc[2][k] + acc[3][k]);

@@ -93,7 +93,8 @@ def lib() -> ctypes.CDLL:
     L.lbm_step.argtypes = [vp, i64]
     L.lbm_get_macros.argtypes = [vp, vp, vp, vp, vp]
     for n in ("lbm_get_pops", "lbm_set_pops", "lbm_get_state", "lbm_set_state", "lbm_conservation",
-              "lbm_adjoint_seed_temperature", "lbm_adjoint_get_lambda", "lbm_adjoint_set_lambda"):
+              "lbm_adjoint_seed_temperature", "lbm_adjoint_get_lambda", "lbm_adjoint_set_lambda",
+              "lbm_adjoint_take_dtau"):
         getattr(L, n).argtypes = [vp, vp]
     L.lbm_loss_temperature.argtypes = [vp, vp, vp]
     L.lbm_adjoint_step.argtypes = [vp, vp, vp]
@@ -138,7 +139,7 @@ def lib() -> ctypes.CDLL:
     for n in ("lbm_create", "lbm_set_tau", "lbm_init", "lbm_init_rt", "lbm_propagate", "lbm_bc",
               "lbm_collide", "lbm_step", "lbm_get_macros", "lbm_get_pops", "lbm_set_pops",
               "lbm_get_state", "lbm_set_state", "lbm_step_state", "lbm_conservation", "lbm_loss_temperature",
-              "lbm_adjoint_seed_temperature", "lbm_adjoint_step", "lbm_adjoint_init_rt",
+              "lbm_adjoint_seed_temperature", "lbm_adjoint_step", "lbm_adjoint_take_dtau", "lbm_adjoint_init_rt",
               "lbm_adjoint_get_lambda", "lbm_adjoint_set_lambda", "lbm_sync"):
         getattr(L, n).restype = st
     _lib = L
@@ -320,10 +321,18 @@ class Lattice:
     def seed_temperature(self, dT):
         self._run("seed_temperature", self.L.lbm_adjoint_seed_temperature, self._field(dT))
 
-    def adjoint_step(self, state: torch.Tensor, dtau_acc: torch.Tensor):
+    def adjoint_step(self, state: torch.Tensor, dtau_acc: torch.Tensor | None):
+        """One reverse step from the snapshot f_n.  Its d/dtau term is added
+        to dtau_acc (a float64 scalar tensor), or, with None, kept in the
+        context until take_dtau."""
         p = _ptr(state, torch.uint8, (self.state_bytes,), self.device)
-        a = _ptr(dtau_acc, torch.float64, (), self.device)
+        a = None if dtau_acc is None else _ptr(dtau_acc, torch.float64, (), self.device)
         self._run("adjoint_step", self.L.lbm_adjoint_step, ctypes.c_void_p(p), ctypes.c_void_p(a))
+
+    def take_dtau(self, dtau_acc: torch.Tensor):
+        """dtau_acc += the d/dtau terms kept by adjoint_step(..., None) calls."""
+        a = _ptr(dtau_acc, torch.float64, (), self.device)
+        self._run("take_dtau", self.L.lbm_adjoint_take_dtau, ctypes.c_void_p(a))
 
     def adjoint_init_rt(self, P, profile: RtProfile | None = None) -> torch.Tensor:
         prof = (profile or RtProfile()).c(self.ly)

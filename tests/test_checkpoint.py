@@ -45,6 +45,8 @@ class FakeLattice:
         self.n = 0
         self.expect = None
         self.steps = 0
+        self.pending = 0       # reverse steps whose d/dtau term is not yet taken
+        self.takes = 0
 
     def new_state(self):
         return FakeState()
@@ -67,7 +69,14 @@ class FakeLattice:
 
     def adjoint_step(self, s, dacc):
         assert s.n == self.expect, (s.n, self.expect)
+        assert dacc is None        # the executor defers the d/dtau terms
         self.expect -= 1
+        self.pending += 1
+
+    def take_dtau(self, dacc):
+        assert self.pending > 0
+        self.pending = 0
+        self.takes += 1
 
 
 @pytest.mark.parametrize("N", [1, 2, 7, 50, 257])
@@ -85,6 +94,7 @@ def test_schedules_feed_every_state_in_reverse_order(N, kind, chain):
     lat.expect = N - 1
     ex.run(bwd)
     assert lat.expect == -1        # all N reverse steps, each with its own f_n
+    assert lat.pending == 0 and lat.takes == 1   # their d/dtau terms taken once, at the end
     assert ex.adjoint_steps == N
     assert ex.forward_steps == sch.forward_steps()
     assert lat.steps == sch.forward_steps() + 1

@@ -421,3 +421,36 @@ def test_adjoint_step_rejects_bad_calls_before_launching():
     plain = Lattice(lx, ly, TAU, device=DEV)
     with pytest.raises(LBMError, match="adjoint buffers"):
         plain.adjoint_step(plain.get_state(), dacc)
+
+
+@pytest.mark.parametrize("precision,lam", [("fp32", "fp64"), ("fp32", "fp32"), ("fp64", "fp64")])
+def test_deferred_dtau_equals_per_step_accumulation(precision, lam):
+    """Reverse steps called without an accumulator keep their d/dtau terms in
+    per-block sums; lbm_adjoint_take_dtau adds them at once.  Over 6 reverse
+    steps that equals per-step accumulation to rounding (1e-14 relative),
+    lambda is bitwise the same, and a second take adds exactly zero."""
+    lx, ly, g, n = 40, 30, -1e-3, 6
+    say(f"deferred dtau {precision} lambda {lam}")
+    P = torch.tensor(inputs.rt_perturbation(lx, ly, 5), device=DEV)
+    out = []
+    for defer in (False, True):
+        lat = Lattice(lx, ly, TAU, g, TB, TT, precision=precision, adjoint=lam, device=DEV)
+        lat.init_rt(P)
+        states = []
+        for _ in range(n):
+            states.append(lat.get_state())
+            lat.step(1)
+        lat.seed_temperature(torch.tensor(inputs.population_noise(lx, ly, 6)[0], device=DEV))
+        dacc = torch.zeros((), dtype=torch.float64, device=DEV)
+        for st in reversed(states):
+            lat.adjoint_step(st, None if defer else dacc)
+        if defer:
+            assert float(dacc) == 0.0
+            lat.take_dtau(dacc)
+            again = torch.full((), 1.5, dtype=torch.float64, device=DEV)
+            lat.take_dtau(again)
+            assert float(again) == 1.5
+        out.append((lat.get_lambda(), dacc))
+    assert torch.equal(out[0][0], out[1][0])
+    a, b = float(out[0][1]), float(out[1][1])
+    assert a != 0.0 and abs(a - b) <= 1e-14 * abs(a), (a, b)
