@@ -251,8 +251,8 @@ def run(args):
     s = lat.stream
     t_fused_runs = [time_launches(lambda: lat.step(1), s, 20) for _ in range(5)]
     t_fused = float(np.median(t_fused_runs))
-    # five more timed runs of 100 steps each: their median, the survey's
-    # protocol, beside the single timed run that gives `value`
+    # five more timed runs of 100 steps each and their median (a protocol
+    # robust to one slow run), beside the single timed run that gives `value`
     median5 = float(np.median([mlups(lat, 100, 0)[0] for _ in range(5)]))
     del lat
     torch.cuda.empty_cache()
