@@ -368,7 +368,9 @@ def run(args):
                                              "fp32_lambda": round(t_adj_pattern["fp32"] / t_adj["fp32"], 3)},
         "adjoint_hbm_frac": {"fp64_lambda": round(740 * sites / t_adj["fp64"] / 1e9 / HBM_PEAK_GBS, 3),
                              "fp32_lambda": round(444 * sites / t_adj["fp32"] / 1e9 / HBM_PEAK_GBS, 3)},
-        "kernel_times": "per-kernel figures: median of 5 runs of 10-20 back-to-back launches (HIP events)",
+        "kernel_times": "per-kernel figures: median of 5 runs of 10-20 back-to-back launches (HIP events); "
+                        "reverse steps as the checkpointed rollout runs them (d/dtau kept per block, "
+                        "reduced once per sweep)",
         "propagate_fp64_hbm_frac_runs": [round(bytes_fp64 / t / 1e9 / HBM_PEAK_GBS, 4) for t in t_prop_runs],
         "hbm_frac": {"fused_fp64": round(bytes_fp64 / t_fused / 1e9 / HBM_PEAK_GBS, 3),
                      "fused_fp32": round(bytes_fp32 / t_fused32 / 1e9 / HBM_PEAK_GBS, 3),
