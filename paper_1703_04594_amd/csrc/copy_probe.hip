@@ -29,8 +29,8 @@
 // site, 37 populations gathered from (x - e_x, y - e_y) of an FP32 state
 // buffer, 37 gathered from (x + e_x, y + e_y) of a lambda buffer (FP32 or
 // FP64), and mu_l = f_l + lambda_l stored at the site, with the reverse
-// step's workgroups and block renumbering (the collide^T arithmetic and the
-// wall terms left out).
+// step's workgroups (64 threads with FP32 lambda, 256 with FP64) and block
+// renumbering (the collide^T arithmetic and the wall terms left out).
 //
 // size_t cp_gather_bytes(int elem_bytes, int lx, int ly)
 //   bytes of one buffer (elem_bytes 8 or 4; lx, ly >= 7; lx ly <= 2^31),
@@ -49,6 +49,7 @@
 #include <cstddef>
 #include <cstdint>
 
+#include "lbm_adjoint.hpp"
 #include "lbm_kernels.hpp"
 
 namespace {
@@ -78,13 +79,12 @@ __global__ __launch_bounds__(lbm::SITE_THREADS) void k_gather_copy(const S* __re
     for (int l = 0; l < NPOP; ++l) st_nt(col + (size_t)l * g.ps, yb, f[l]);
 }
 
-template <typename L>
-__global__ __launch_bounds__(lbm::SITE_THREADS) void k_adjoint_pattern(const float* __restrict__ f,
-                                                                      const L* __restrict__ lam, L* __restrict__ mu,
-                                                                      lbm::Geo g, lbm::Geo lg)
+template <typename L, int T = lbm::adj_threads<L>()>
+__global__ __launch_bounds__(T) void k_adjoint_pattern(const float* __restrict__ f, const L* __restrict__ lam,
+                                                       L* __restrict__ mu, lbm::Geo g, lbm::Geo lg)
 {
     using namespace lbm;
-    const SiteBlock sb = site_block(g);
+    const SiteBlock sb = site_block<true, T>(g);
     const int x = sb.x, y = sb.y;
     if (y >= g.ly) return;
     const unsigned yb = (unsigned)y * 4u, yd = (unsigned)y * (unsigned)sizeof(L);
@@ -196,13 +196,18 @@ extern "C" int cp_adjoint_pattern(int lam_bytes, int lx, int ly, const void* f, 
         return a < b + m && b < a + n;
     };
     if (overlap(f, nf, lam, nl) || overlap(f, nf, mu, nl) || overlap(lam, nl, mu, nl)) return 1;
-    const dim3 grid((unsigned)((ly + lbm::SITE_THREADS - 1) / lbm::SITE_THREADS) * (unsigned)lx);
     hipStream_t s = (hipStream_t)stream;
-    if (lam_bytes == 8)
-        hipLaunchKernelGGL((k_adjoint_pattern<double>), grid, dim3(lbm::SITE_THREADS), 0, s, (const float*)f,
-                           (const double*)lam, (double*)mu, g, lg);
-    else
-        hipLaunchKernelGGL((k_adjoint_pattern<float>), grid, dim3(lbm::SITE_THREADS), 0, s, (const float*)f,
-                           (const float*)lam, (float*)mu, g, lg);
+    // the reverse step's block size for this lambda storage
+    if (lam_bytes == 8) {
+        constexpr int T = lbm::adj_threads<double>();
+        const dim3 grid((unsigned)((ly + T - 1) / T) * (unsigned)lx);
+        hipLaunchKernelGGL((k_adjoint_pattern<double>), grid, dim3(T), 0, s, (const float*)f, (const double*)lam,
+                           (double*)mu, g, lg);
+    } else {
+        constexpr int T = lbm::adj_threads<float>();
+        const dim3 grid((unsigned)((ly + T - 1) / T) * (unsigned)lx);
+        hipLaunchKernelGGL((k_adjoint_pattern<float>), grid, dim3(T), 0, s, (const float*)f, (const float*)lam,
+                           (float*)mu, g, lg);
+    }
     return hipGetLastError() == hipSuccess ? 0 : 2;
 }

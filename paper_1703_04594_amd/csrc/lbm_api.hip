@@ -74,7 +74,10 @@ Plan plan(const lbm_params* p)
         const size_t lb = align_up((size_t)pl.lgeo.total * (p->adjoint == 2 ? 4 : 8), ALIGN);
         pl.off_lam[0] = off; off += lb;
         pl.off_lam[1] = off; off += lb;
-        const size_t nb = (size_t)((p->ly + SITE_THREADS - 1) / SITE_THREADS) * p->lx;
+        // one partial per block of the reverse step (its blocks are the
+        // smallest of the adjoint launches)
+        const int at = p->adjoint == 2 ? adj_threads<float>() : adj_threads<double>();
+        const size_t nb = (size_t)((p->ly + at - 1) / at) * p->lx;
         pl.off_apart = off; off += align_up(nb * 8, ALIGN);
         pl.off_adacc = off; off += align_up(nb * 8, ALIGN);
     }
@@ -524,7 +527,7 @@ template <typename S, typename L>
 int adj_blocks_per_cu_t()
 {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_adj_collide<S, L, true, true>, SITE_THREADS, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_adj_collide<S, L, true, true>, adj_threads<L>(), 0) !=
         hipSuccess)
         return 0;
     return n;
@@ -591,7 +594,8 @@ lbm_status lbm_create(const lbm_params* p, void* dev_workspace, size_t bytes, vo
             c->collide_lds = coll;
     }
     c->adj_lds = 0;
-    if (p->adjoint && ncu > 0 && (size_t)max_lds >= ADJ_LDS_RESERVE) {
+    // (256-thread reverse steps only: FP64 lambda)
+    if (p->adjoint == 1 && ncu > 0 && (size_t)max_lds >= ADJ_LDS_RESERVE) {
         const int full = adj_blocks_per_cu(p);
         const size_t nb = site_grid(pl.geo).x;
         auto rounds = [&](int per_cu) { return (nb + (size_t)per_cu * ncu - 1) / ((size_t)per_cu * ncu); };

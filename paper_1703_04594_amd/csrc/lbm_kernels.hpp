@@ -117,17 +117,18 @@ __device__ __forceinline__ int xcd_block(int b, int n)
     return k * q + (k < r ? k : r) + i;
 }
 
-// Site kernels: block L covers sites y in [bx * SITE_THREADS, ...) of column x.
+// Site kernels: block L covers sites y in [bx * T, ...) of column x, T the
+// block's threads (SITE_THREADS, except the reverse step with FP32 lambda).
 // (Measured: the renumbering gains 5% on the FP64 step and 14% on the
 // adjoint step, but costs ~1% on the FP32 step, which therefore keeps the
 // hardware order.)
 struct SiteBlock { int x, y; };
-template <bool REMAP = true>
+template <bool REMAP = true, int T = SITE_THREADS>
 __device__ __forceinline__ SiteBlock site_block(const Geo& g)
 {
-    const int nyb = (g.ly + SITE_THREADS - 1) / SITE_THREADS;
+    const int nyb = (g.ly + T - 1) / T;
     const int L = REMAP ? xcd_block(blockIdx.x, nyb * g.lx) : (int)blockIdx.x;
-    return SiteBlock{L / nyb, (L % nyb) * SITE_THREADS + (int)threadIdx.x};
+    return SiteBlock{L / nyb, (L % nyb) * T + (int)threadIdx.x};
 }
 
 // Plane access as (block-uniform base pointer) + (per-thread 32-bit byte
@@ -351,12 +352,13 @@ constexpr unsigned FUSED_FP64_CAP_MIN_BLOCKS_PER_CU = 16;
 // slower at 2048x4096 and 4096x4096.
 constexpr unsigned COLLIDE_FP64_LDS_RESERVE = 96 * 1024;
 constexpr unsigned COLLIDE_FP32_LDS_RESERVE = 64 * 1024;
-// The reverse step (k_adj_collide, 3 blocks per CU by its registers) takes a
-// reserve that leaves 2 blocks per CU only when that does not add a round of
-// blocks: rounds = ceil(blocks / (blocks per CU x CUs)).  That holds on small
-// lattices alone (up to 4 blocks per CU), e.g. 512x512, where it runs 12%
-// (FP64 lambda) and 2% (FP32 lambda) faster; wherever the cap adds a round it
-// cost 3-60% (sweep from 256x256 to 2048x4096).
+// The reverse step with FP64 lambda (256-thread blocks, 3 per CU by its
+// registers) takes a reserve that leaves 2 blocks per CU only when that does
+// not add a round of blocks: rounds = ceil(blocks / (blocks per CU x CUs)).
+// That holds on small lattices alone (up to 4 blocks per CU), e.g. 512x512,
+// where it runs 12% faster; wherever the cap adds a round it cost 3-60%
+// (sweep from 256x256 to 2048x4096).  With FP32 lambda the reverse step runs
+// 64-thread blocks and no cap.
 constexpr unsigned ADJ_LDS_RESERVE = 64 * 1024;
 constexpr int ADJ_CAP_BLOCKS_PER_CU = 2;
 template <typename S, bool WRAP, bool WALLS, bool WIDE = true>
