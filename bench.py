@@ -380,8 +380,8 @@ def run(args):
             "fused_fp64": flop_fraction("lbm::k_step_fused<double, true, true, true>", t_fused),
             "collide_fp64": flop_fraction("lbm::k_collide<double, true, true>", t_coll),
             "fused_fp32": flop_fraction("lbm::k_step_fused<float, true, true, true>", t_fused32),
-            "adjoint_fp64_lambda": flop_fraction("lbm::k_adj_collide<float, double, true, true>", t_adj["fp64"]),
-            "adjoint_fp32_lambda": flop_fraction("lbm::k_adj_collide<float, float, true, true>", t_adj["fp32"])},
+            "adjoint_fp64_lambda": flop_fraction("lbm::k_adj_collide<float, double, true, true, 256>", t_adj["fp64"]),
+            "adjoint_fp32_lambda": flop_fraction("lbm::k_adj_collide<float, float, true, true, 64>", t_adj["fp32"])},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic("lbm::k_step_fused<double, true, true, true>") if (lx, ly) == (2048, 4096) else None,
