@@ -398,7 +398,8 @@ def test_reverse_step_over_f32sums_states_equals_fp32():
 def test_adjoint_step_rejects_bad_calls_before_launching():
     """lbm_adjoint_step's host checks: no seed yet (state error), a
     misaligned snapshot, a context without adjoint buffers; nothing is
-    launched, and a valid call afterwards still works."""
+    launched, and a valid call afterwards still works.  lbm_adjoint_take_dtau
+    rejects a NULL accumulator and a context without adjoint buffers."""
     from paper_1703_04594_amd.lbm import LBMError
     lx, ly = 24, 20
     say("adjoint_step host checks")
@@ -418,9 +419,12 @@ def test_adjoint_step_rejects_bad_calls_before_launching():
     lat.adjoint_step(st, dacc)
     lat.sync()
     assert torch.isfinite(dacc).item() and torch.isfinite(lat.get_lambda()).all().item()
+    assert lat.L.lbm_adjoint_take_dtau(lat.h, None) == 1      # LBM_ERR_INVALID: NULL accumulator
     plain = Lattice(lx, ly, TAU, device=DEV)
     with pytest.raises(LBMError, match="adjoint buffers"):
         plain.adjoint_step(plain.get_state(), dacc)
+    with pytest.raises(LBMError, match="adjoint buffers"):
+        plain.take_dtau(dacc)
 
 
 @pytest.mark.parametrize("precision,lam", [("fp32", "fp64"), ("fp32", "fp32"), ("fp64", "fp64")])
