@@ -6,7 +6,9 @@ displacement field P.  Its backward seeds the adjoint with the incoming
 dL/dT_N (lbm_adjoint_seed_temperature), reverses the N steps with the chosen
 checkpoint schedule (lbm_adjoint_step per step, replaying forward segments
 from stored states), and maps lambda_0 to dL/dP (lbm_adjoint_init_rt); the
-d/dtau terms of every step accumulate in one FP64 device scalar.
+d/dtau terms of every step are kept in per-block FP64 sums in the lattice and
+added to one FP64 device scalar at the end of the sweep
+(lbm_adjoint_take_dtau).
 
 Forward states may be FP32-shifted (the adjoint then linearises around the
 stored FP32 states, in FP64) or FP64.

@@ -458,3 +458,38 @@ def test_deferred_dtau_equals_per_step_accumulation(precision, lam):
     assert torch.equal(out[0][0], out[1][0])
     a, b = float(out[0][1]), float(out[1][1])
     assert a != 0.0 and abs(a - b) <= 1e-14 * abs(a), (a, b)
+
+
+@pytest.mark.parametrize("lam", ["fp64", "fp32"])
+def test_manual_reverse_sweep_equals_the_rollout_bitwise(lam):
+    """The reverse sweep written out by hand (every state kept, lattice steps,
+    reverse steps with deferred d/dtau, one take, init^T) gives bitwise the
+    gradients of the autograd rollout under a checkpoint schedule: the
+    schedule only changes how the forward states are recomputed."""
+    lx, ly, n = 36, 28, 14
+    say(f"manual sweep vs rollout, lambda {lam}")
+    P = torch.tensor(inputs.rt_perturbation(lx, ly, 12) + 0.2 * inputs.uniform_field(lx, ly, 13, -1, 1))
+    Tt = torch.tensor(inputs.uniform_field(lx, ly, 14, 0.7, 1.3)).to(DEV)
+    cfg = RolloutConfig(lx, ly, n, precision="fp32", checkpoint="binomial", slots=3, lambda_precision=lam)
+    Pg = P.to(DEV).requires_grad_(True)
+    tg = torch.tensor(TAU, dtype=torch.float64, device=DEV, requires_grad=True)
+    T = rt_temperature(Pg, tg, cfg)
+    (0.5 * ((T - Tt) ** 2).sum()).backward()
+
+    lat = Lattice(lx, ly, TAU, cfg.g_y, cfg.t_bottom, cfg.t_top, precision="fp32", step="fused",
+                  adjoint=lam, device=DEV)
+    Pd = P.to(DEV)
+    lat.init_rt(Pd)
+    states = []
+    for _ in range(n):
+        states.append(lat.get_state())
+        lat.step(1)
+    Tn = lat.macros()[3]
+    assert torch.equal(Tn, T.detach())
+    lat.seed_temperature((Tn - Tt).contiguous())
+    for st in reversed(states):
+        lat.adjoint_step(st, None)
+    dtau = torch.zeros((), dtype=torch.float64, device=DEV)
+    lat.take_dtau(dtau)
+    dP = lat.adjoint_init_rt(Pd)
+    assert torch.equal(dP, Pg.grad) and torch.equal(dtau, tg.grad)
