@@ -19,9 +19,9 @@
 // arithmetic: on a padded columns-layout buffer of the library (the geometry
 // of lbm_kernels.hpp), every site gathers its 37 populations from
 // (x - e_x mod lx, y - e_y) and stores them at its own site, with the same
-// workgroups, block renumbering, load priority, store form and (FP64, large
-// lattices) occupancy cap as the FP64 / FP32 fused step (walls and the
-// collision left out).  It is the streaming of eq. (4) evaluated per site, so
+// workgroups (block size and, FP64 on large lattices, occupancy cap), block
+// renumbering, load priority and store form as the FP64 / FP32 fused step
+// (walls and the collision left out).  It is the streaming of eq. (4) evaluated per site, so
 // dst equals a propagate of src.  Its time is the ceiling that access pattern
 // leaves the fused step.
 //
@@ -54,12 +54,11 @@
 
 namespace {
 
-template <typename S>
-__global__ __launch_bounds__(lbm::SITE_THREADS) void k_gather_copy(const S* __restrict__ src, S* __restrict__ dst,
-                                                                  lbm::Geo g)
+template <typename S, int T = lbm::SITE_THREADS>
+__global__ __launch_bounds__(T) void k_gather_copy(const S* __restrict__ src, S* __restrict__ dst, lbm::Geo g)
 {
     using namespace lbm;
-    const SiteBlock sb = site_block<sizeof(S) == 8>(g);
+    const SiteBlock sb = site_block<sizeof(S) == 8, T>(g);
     const int x = sb.x, y = sb.y;
     if (y >= g.ly) return;
     const unsigned yb = (unsigned)y * (unsigned)sizeof(S);
@@ -163,21 +162,27 @@ extern "C" int cp_gather_copy(int elem_bytes, int lx, int ly, const void* src, v
     if (a < b + bytes && b < a + bytes) return 1;   // overlapping buffers
     const dim3 grid((unsigned)((ly + lbm::SITE_THREADS - 1) / lbm::SITE_THREADS) * (unsigned)lx);
     hipStream_t s = (hipStream_t)stream;
-    // the FP64 fused step's occupancy cap (lbm_kernels.hpp), by the same rule
-    unsigned lds = 0;
-    int dev = 0, ncu = 0, max_lds = 0;
-    if (elem_bytes == 8 && hipGetDevice(&dev) == hipSuccess &&
-        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
-        hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
-        (size_t)max_lds >= lbm::FUSED_FP64_LDS_RESERVE && ncu > 0 &&
-        (size_t)grid.x >= (size_t)lbm::FUSED_FP64_CAP_MIN_BLOCKS_PER_CU * (size_t)ncu)
-        lds = lbm::FUSED_FP64_LDS_RESERVE;
-    if (elem_bytes == 8)
-        hipLaunchKernelGGL((k_gather_copy<double>), grid, dim3(lbm::SITE_THREADS), lds, s, (const double*)src,
-                           (double*)dst, g);
-    else
+    if (elem_bytes == 4) {
         hipLaunchKernelGGL((k_gather_copy<float>), grid, dim3(lbm::SITE_THREADS), 0, s, (const float*)src,
                            (float*)dst, g);
+        return hipGetLastError() == hipSuccess ? 0 : 2;
+    }
+    // the FP64 fused step's launch settings (lbm_kernels.hpp), by the same rule
+    lbm::FusedLaunch fl{lbm::SITE_THREADS, 0u};
+    int dev = 0, ncu = 0, max_lds = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess)
+        fl = lbm::fused_fp64_launch(grid.x, ncu, max_lds);
+    if (fl.threads == lbm::FUSED_FP64_WIDE_THREADS) {
+        constexpr int T = lbm::FUSED_FP64_WIDE_THREADS;
+        const dim3 wgrid((unsigned)((ly + T - 1) / T) * (unsigned)lx);
+        hipLaunchKernelGGL((k_gather_copy<double, T>), wgrid, dim3(T), fl.lds, s, (const double*)src,
+                           (double*)dst, g);
+    } else {
+        hipLaunchKernelGGL((k_gather_copy<double>), grid, dim3(lbm::SITE_THREADS), fl.lds, s, (const double*)src,
+                           (double*)dst, g);
+    }
     return hipGetLastError() == hipSuccess ? 0 : 2;
 }
 

@@ -109,6 +109,7 @@ struct lbm_ctx {
     WallTable wt;
     CollideArgs cargs;
     unsigned fused_lds;  // dynamic LDS of the fused step's launch (occupancy cap; 0: none)
+    int fused_threads;   // threads per block of the FP64 fused step (256 or 512)
     unsigned collide_lds;// the same for the split step's collide
     unsigned adj_lds;    // the same for the reverse step
     std::string err;
@@ -283,22 +284,24 @@ lbm_status do_collide(lbm_ctx* c)
     return check_launch(c, "collide");
 }
 
-// One fused step src -> dst (wall densities read from wr, written to wo).
-template <typename S, bool WIDE>
+// One fused step src -> dst (wall densities read from wr, written to wo),
+// T threads per block.
+template <typename S, bool WIDE, int T>
 void launch_fused_kernel(lbm_ctx* c, const S* src, S* dst, const double* wr, double* wo)
 {
     const Geo& g = c->pl.geo;
     const bool walls = c->p.ybc == LBM_Y_WALLS;
     const bool wrap = c->p.xmode == LBM_X_WRAP;
     const unsigned lds = sizeof(S) == 8 ? c->fused_lds : 0u;
+    const dim3 grid((unsigned)((g.ly + T - 1) / T) * (unsigned)g.lx);
     if (wrap && walls)
-        hipLaunchKernelGGL((k_step_fused<S, true, true, WIDE>), site_grid(g), dim3(SITE_THREADS), lds, c->stream, src, dst, g, c->cargs, wr, c->wt, wo);
+        hipLaunchKernelGGL((k_step_fused<S, true, true, WIDE, T>), grid, dim3(T), lds, c->stream, src, dst, g, c->cargs, wr, c->wt, wo);
     else if (wrap)
-        hipLaunchKernelGGL((k_step_fused<S, true, false, WIDE>), site_grid(g), dim3(SITE_THREADS), lds, c->stream, src, dst, g, c->cargs, wr, c->wt, wo);
+        hipLaunchKernelGGL((k_step_fused<S, true, false, WIDE, T>), grid, dim3(T), lds, c->stream, src, dst, g, c->cargs, wr, c->wt, wo);
     else if (walls)
-        hipLaunchKernelGGL((k_step_fused<S, false, true, WIDE>), site_grid(g), dim3(SITE_THREADS), lds, c->stream, src, dst, g, c->cargs, wr, c->wt, wo);
+        hipLaunchKernelGGL((k_step_fused<S, false, true, WIDE, T>), grid, dim3(T), lds, c->stream, src, dst, g, c->cargs, wr, c->wt, wo);
     else
-        hipLaunchKernelGGL((k_step_fused<S, false, false, WIDE>), site_grid(g), dim3(SITE_THREADS), lds, c->stream, src, dst, g, c->cargs, wr, c->wt, wo);
+        hipLaunchKernelGGL((k_step_fused<S, false, false, WIDE, T>), grid, dim3(T), lds, c->stream, src, dst, g, c->cargs, wr, c->wt, wo);
 }
 
 template <typename S>
@@ -306,11 +309,16 @@ void launch_fused(lbm_ctx* c, const S* src, S* dst, const double* wr, double* wo
 {
     if constexpr (std::is_same<S, float>::value) {
         if (c->f32_sums()) {
-            launch_fused_kernel<S, false>(c, src, dst, wr, wo);
+            launch_fused_kernel<S, false, SITE_THREADS>(c, src, dst, wr, wo);
             return;
         }
+        launch_fused_kernel<S, true, SITE_THREADS>(c, src, dst, wr, wo);
+    } else {
+        if (c->fused_threads == FUSED_FP64_WIDE_THREADS)
+            launch_fused_kernel<S, true, FUSED_FP64_WIDE_THREADS>(c, src, dst, wr, wo);
+        else
+            launch_fused_kernel<S, true, SITE_THREADS>(c, src, dst, wr, wo);
     }
-    launch_fused_kernel<S, true>(c, src, dst, wr, wo);
 }
 
 template <typename S>
@@ -582,16 +590,20 @@ lbm_status lbm_create(const lbm_params* p, void* dev_workspace, size_t bytes, vo
     // occupancy caps of the FP64 fused step and of the collide on large
     // lattices (lbm_kernels.hpp)
     c->fused_lds = 0;
+    c->fused_threads = SITE_THREADS;
     c->collide_lds = 0;
     int dev = 0, ncu = 0, max_lds = 0;
     if (hipGetDevice(&dev) == hipSuccess &&
         hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
-        hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && ncu > 0 &&
-        (size_t)site_grid(pl.geo).x >= (size_t)FUSED_FP64_CAP_MIN_BLOCKS_PER_CU * (size_t)ncu) {
-        const unsigned coll = p->precision == LBM_FP64 ? COLLIDE_FP64_LDS_RESERVE : COLLIDE_FP32_LDS_RESERVE;
-        if ((size_t)max_lds >= FUSED_FP64_LDS_RESERVE) c->fused_lds = FUSED_FP64_LDS_RESERVE;
-        if ((size_t)max_lds >= coll && (p->precision != LBM_FP64 || p->layout == LBM_LAYOUT_COLUMNS))
-            c->collide_lds = coll;
+        hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && ncu > 0) {
+        const FusedLaunch fl = fused_fp64_launch(site_grid(pl.geo).x, ncu, max_lds);
+        c->fused_threads = fl.threads;
+        c->fused_lds = fl.lds;
+        if ((size_t)site_grid(pl.geo).x >= (size_t)FUSED_FP64_CAP_MIN_BLOCKS_PER_CU * (size_t)ncu) {
+            const unsigned coll = p->precision == LBM_FP64 ? COLLIDE_FP64_LDS_RESERVE : COLLIDE_FP32_LDS_RESERVE;
+            if ((size_t)max_lds >= coll && (p->precision != LBM_FP64 || p->layout == LBM_LAYOUT_COLUMNS))
+                c->collide_lds = coll;
+        }
     }
     c->adj_lds = 0;
     // (256-thread reverse steps only: FP64 lambda)

@@ -338,10 +338,33 @@ __global__ __launch_bounds__(SITE_THREADS) void k_collide(S* __restrict__ buf, G
 // 1024x2048 to 4096x4096 for any reserve from 56 to 72 KB; no change at
 // 1024x1024; 13% slower at 512x512, whose 1024 blocks no longer fit one
 // round.  The FP32 step and the other kernels measured slower capped.
+// On the largest lattices (from 64 blocks of 256 sites per CU) the FP64 step
+// runs 512-thread blocks, one per CU (96 KB reserve): 0.7% faster at
+// 2048x4096 and 4096x4096 and 1.2% at 2160x8192, but 3.5% slower at
+// 1024x2048 (same A/B, two runs each), so smaller lattices keep the
+// 256-thread form.
 // ---------------------------------------------------------------------------
 constexpr unsigned FUSED_FP64_LDS_RESERVE = 64 * 1024;
-// the cap is applied from this many site blocks per CU on
+// the cap is applied from this many site blocks (of SITE_THREADS) per CU on
 constexpr unsigned FUSED_FP64_CAP_MIN_BLOCKS_PER_CU = 16;
+constexpr int FUSED_FP64_WIDE_THREADS = 512;
+constexpr unsigned FUSED_FP64_WIDE_LDS_RESERVE = 96 * 1024;
+constexpr unsigned FUSED_FP64_WIDE_MIN_BLOCKS_PER_CU = 64;
+
+// Launch settings of the FP64 fused step (and of its access-pattern probe)
+// for a lattice of nb256 blocks of SITE_THREADS sites on a GPU of ncu CUs
+// with max_lds bytes of LDS per block: threads per block and dynamic LDS.
+struct FusedLaunch { int threads; unsigned lds; };
+inline FusedLaunch fused_fp64_launch(size_t nb256, int ncu, int max_lds)
+{
+    if (ncu > 0 && nb256 >= (size_t)FUSED_FP64_WIDE_MIN_BLOCKS_PER_CU * (size_t)ncu &&
+        (size_t)max_lds >= FUSED_FP64_WIDE_LDS_RESERVE)
+        return {FUSED_FP64_WIDE_THREADS, FUSED_FP64_WIDE_LDS_RESERVE};
+    if (ncu > 0 && nb256 >= (size_t)FUSED_FP64_CAP_MIN_BLOCKS_PER_CU * (size_t)ncu &&
+        (size_t)max_lds >= FUSED_FP64_LDS_RESERVE)
+        return {SITE_THREADS, FUSED_FP64_LDS_RESERVE};
+    return {SITE_THREADS, 0u};
+}
 // The in-place collide of the split step takes the same kind of cap on large
 // lattices: 2 blocks per CU in FP32 (64 KB; 1-5% faster from 1024x2048 on, in
 // both layouts) and, in the columns layout, 1 block per CU in FP64 (96 KB;
@@ -361,13 +384,13 @@ constexpr unsigned COLLIDE_FP32_LDS_RESERVE = 64 * 1024;
 // 64-thread blocks and no cap.
 constexpr unsigned ADJ_LDS_RESERVE = 64 * 1024;
 constexpr int ADJ_CAP_BLOCKS_PER_CU = 2;
-template <typename S, bool WRAP, bool WALLS, bool WIDE = true>
-__global__ __launch_bounds__(SITE_THREADS) void k_step_fused(const S* __restrict__ src, S* __restrict__ dst, Geo g,
+template <typename S, bool WRAP, bool WALLS, bool WIDE = true, int T = SITE_THREADS>
+__global__ __launch_bounds__(T) void k_step_fused(const S* __restrict__ src, S* __restrict__ dst, Geo g,
                                                           CollideArgs args, const double* __restrict__ wall_rho, WallTable wt,
                                                           double* __restrict__ wall_rho_out)
 {
     using Cc = typename Store<S>::C;
-    const SiteBlock sb = site_block<sizeof(S) == 8>(g);
+    const SiteBlock sb = site_block<sizeof(S) == 8, T>(g);
     const int x = sb.x, y = sb.y;
     if (y >= g.ly) return;
     const unsigned yb = (unsigned)y * (unsigned)sizeof(S);

@@ -42,9 +42,11 @@ def aligned_copy(t, n):
     return raw, buf
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
-@pytest.mark.parametrize("lx,ly", [(37, 45), (300, 1030)])
+@pytest.mark.parametrize("precision,lx,ly", [(p, lx, ly) for p in ("fp64", "fp32") for lx, ly in ((37, 45), (300, 1030))]
+                         + [("fp64", 2048, 4096)])
 def test_gather_copy_is_the_library_propagate(precision, lx, ly):
+    """2048x4096 FP64 takes the probe's 512-thread, one-block-per-CU launch
+    (the fused step's on the largest lattices)."""
     say(f"cp_gather_copy {precision} {lx}x{ly}")
     P = probe_lib()
     elem = 8 if precision == "fp64" else 4
