@@ -233,8 +233,17 @@ def test_step_state_equals_step(precision, ybc, xmode):
     set_state + lbm_step + get_state gives, chained over two steps, with the
     same wall densities, and leaves the context's own state alone;
     overlapping snapshots are refused."""
-    lx, ly = 40, 33
-    say(f"step_state {precision} {ybc} {xmode}")
+    check_step_state(precision, ybc, xmode, 40, 33)
+
+
+def test_step_state_equals_step_with_the_wide_fused_launch():
+    """The same at 2048x4096 FP64, where the fused step (and so step_state)
+    runs 512-thread blocks with an LDS reserve."""
+    check_step_state("fp64", "walls", "wrap", 2048, 4096)
+
+
+def check_step_state(precision, ybc, xmode, lx, ly):
+    say(f"step_state {precision} {ybc} {xmode} {lx}x{ly}")
     P = inputs.rt_perturbation(lx, ly, 5)
     lat = Lattice(lx, ly, TAU, G, TB, TT, precision=precision, ybc=ybc, xmode=xmode, step="fused", device=DEV)
     lat.init_rt(tg(P))
