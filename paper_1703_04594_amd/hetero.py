@@ -3,15 +3,15 @@ auto-tuning (host-side logic; the stepping itself is lbm.Hetero, native).
 
 The lattice is split along x: m border columns on each side run on the
 host's cores, the other lx - 2m on the GPU, and three-column halos are
-swapped after every step.  The model (eq. (perf-model), one process, so no
-inter-process term) is
+swapped after every step.  The performance model of section 6 (one process,
+so no inter-process term) is
 
     T_exe(m) = max(T_acc, T_host) + T_swap
     T_acc    = (lx - 2m) ly tau_d
     T_host   = 2m ly tau_h
 
 with T_swap independent of m (and absent when m = 0: nothing is split).
-T_exe is least where T_acc = T_host (eq. (param-tuning)):
+T_exe is least where T_acc = T_host (the tuning condition of section 6):
 2m* = lx tau_d / (tau_d + tau_h).  The auto-tuner measures tau_d, tau_h and
 T_swap with short runs and evaluates the model.
 
