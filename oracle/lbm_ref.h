@@ -11,7 +11,7 @@
  * Tripiccione, "Optimization of Lattice Boltzmann Simulations on Heterogeneous
  * Computers", arXiv:1703.04594), section 3 ("Lattice Boltzmann methods"):
  *   - the BGK evolution equation, eq. (1);
- *   - the macroscopic moments rho, rho*u, D*rho*T, eq. (2) (eq:macro);
+ *   - the macroscopic moments rho, rho*u, D*rho*T, eq. (2);
  *   - the pull form of the update, eq. (4): gather then compute;
  *   - the per-step order propagate -> bc -> collide (section 5, the
  *     heterogeneous control flow).
