@@ -272,6 +272,29 @@ def check_step_state(precision, ybc, xmode, lx, ly):
         lat.step_state(s1, s1)                            # overlapping snapshots
 
 
+@pytest.mark.parametrize("ybc,xmode,layout", [("periodic", "halo", "planes"), ("walls", "halo", "columns"),
+                                                ("periodic", "wrap", "columns")])
+def test_wide_fused_launch_matches_the_split_step(ybc, xmode, layout):
+    """At 2048x4096 the FP64 fused step runs its 512-thread launch; in the
+    boundary modes and layouts the full-size run does not use, 10 fused
+    steps agree with 10 split steps (propagate, bc, collide: other kernels)
+    to 1e-13 of w_l on every population of every site."""
+    lx, ly, n = 2048, 4096, 10
+    say(f"wide fused vs split {ybc} {xmode} {layout}")
+    P = tg(inputs.rt_perturbation(lx, ly, 7))
+    out = []
+    for step in ("fused", "split"):
+        lat = Lattice(lx, ly, TAU, G, TB, TT, ybc=ybc, xmode=xmode, step=step, layout=layout, device=DEV)
+        lat.init_rt(P)
+        lat.step(n)
+        out.append(lat.get_pops())
+        del lat
+    wc = torch.tensor(WC, device=DEV)
+    err = float(((out[0] - out[1]).abs() / wc).max())
+    say(f"  max |f_fused - f_split| / w = {err:.2e}")
+    assert err <= 1e-13, err
+
+
 def test_split_calls_equal_step():
     lx, ly = 50, 40
     f0 = random_state(lx, ly, 9)
