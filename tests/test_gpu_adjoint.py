@@ -493,3 +493,45 @@ def test_manual_reverse_sweep_equals_the_rollout_bitwise(lam):
     lat.take_dtau(dtau)
     dP = lat.adjoint_init_rt(Pd)
     assert torch.equal(dP, Pg.grad) and torch.equal(dtau, tg.grad)
+
+
+def test_1024x2048_10000_step_gradient_against_central_differences():
+    """The at-scale adjoint configuration's size and length (1024x2048, 10,000
+    steps, binomial checkpointing, here with 20 slots) in FP64: the adjoint's
+    dL/dP along 3 unit-RMS probes against Richardson-extrapolated central
+    differences (eps = 1e-4 and 5e-5) to 1e-6 (measured <= 2e-8), and dL/dtau
+    to 1e-3 (measured 9e-5).  The tau bar is loose by necessity: the loss
+    (1.4e-8) sums squares of T_N - T* ~ 1e-7 per site, differences of values
+    ~1, so the FP64 forward leaves it ~1e-7 relative round-off, and a tau
+    difference changes it by only 2 eps dL/dtau ~ 5e-11 (eps = 1e-5): the
+    quotient cannot resolve better than ~1e-4.  dL/dP moves the loss ~200x more
+    per step and stays clear of that floor."""
+    lx, ly, n = 1024, 2048, 10000
+    say("1024x2048 10000-step FD check")
+    P = torch.tensor(inputs.rt_perturbation(lx, ly, 1), device=DEV)
+    Tt = final_T("fp64", inputs.rt_perturbation(lx, ly, 2), lx, ly, n)
+    cfg = RolloutConfig(lx, ly, n, precision="fp64", checkpoint="binomial", slots=20)
+    Pg = P.clone().requires_grad_(True)
+    tg = torch.tensor(TAU, dtype=torch.float64, device=DEV, requires_grad=True)
+    T = rt_temperature(Pg, tg, cfg)
+    (0.5 * ((T - Tt) ** 2).sum()).backward()
+    gP, gtau = Pg.grad.clone(), float(tg.grad)
+    say(f"  stats {cfg.stats}")
+    probes = torch.tensor(inputs.probe_directions(lx, ly, 77, 3, norm="rms"), device=DEV)
+
+    def rich(f, eps):
+        d1 = (f(eps) - f(-eps)) / (2 * eps)
+        d2 = (f(eps / 2) - f(-eps / 2)) / eps
+        return (4 * d2 - d1) / 3
+
+    for k in range(3):
+        v = probes[k]
+        r = rich(lambda h: fp64_loss(P + h * v, TAU, Tt, lx, ly, n), 1e-4)
+        ad = float((gP * v).sum())
+        e = abs(r - ad) / abs(ad)
+        say(f"  probe {k}: adjoint {ad:.10e} richardson {r:.10e} rel {e:.1e}")
+        assert e <= 1e-6, (k, e)
+    r = rich(lambda h: fp64_loss(P, TAU + h, Tt, lx, ly, n), 1e-5)
+    e = abs(r - gtau) / abs(gtau)
+    say(f"  tau: adjoint {gtau:.10e} richardson {r:.10e} rel {e:.1e}")
+    assert e <= 1e-3, e
