@@ -11,7 +11,7 @@ import pytest
 import torch
 
 import oracle
-from paper_1703_04594_amd import inputs
+from paper_1703_04594_amd import inputs, lbm
 from paper_1703_04594_amd.lbm import Lattice
 
 from _util import G, TAU, TB, TT, W, WC, oracle_rt, oracle_window_site, say
@@ -606,3 +606,24 @@ def test_fp32_forms_at_full_size_over_5000_steps():
             e_u = float((torch.stack([b[1], b[2]]) - u64).norm() / u64.norm())
             say(f"  step {(k + 1) * every} {prec}: rho {e_rho:.2e} T {e_T:.2e} u {e_u:.2e}")
             assert e_rho <= bar and e_T <= bar and e_u <= bar_u, (prec, k, e_rho, e_T, e_u)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_a_nan_in_the_state_shows_in_the_totals(precision):
+    """Failure detection: one non-finite population anywhere makes the FP64
+    lattice totals non-finite (lbm_conservation and the no-alloc entry point),
+    before and after further steps, so a periodic check of the totals catches
+    a blown-up run.  A finite state gives finite totals."""
+    lx, ly = 64, 48
+    say(f"nan detection {precision}")
+    lat = Lattice(lx, ly, TAU, G, TB, TT, precision=precision, step="fused", device=DEV)
+    lat.init_rt(tg(inputs.rt_perturbation(lx, ly, 3)))
+    lat.step(3)
+    assert bool(torch.isfinite(lat.conservation()).all())
+    f = lat.get_pops()
+    f[17, 40, 30] = float("nan")
+    lat.set_pops(f)
+    assert not bool(torch.isfinite(lat.conservation()).all())
+    assert not bool(torch.isfinite(lbm.conservation_noalloc(lat.get_pops())).all())
+    lat.step(5)
+    assert not bool(torch.isfinite(lat.conservation()).all())
