@@ -627,3 +627,22 @@ def test_a_nan_in_the_state_shows_in_the_totals(precision):
     assert not bool(torch.isfinite(lbm.conservation_noalloc(lat.get_pops())).all())
     lat.step(5)
     assert not bool(torch.isfinite(lat.conservation()).all())
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("step", ["fused", "split"])
+def test_runs_are_bitwise_reproducible(precision, step):
+    """Determinism (no atomics in the forward, fixed reduction orders): two
+    independent contexts given the same input give bitwise the same state and
+    totals after 100 steps, which checkpoint replays rely on."""
+    lx, ly = 512, 512
+    say(f"reproducible {precision} {step}")
+    P = tg(inputs.rt_perturbation(lx, ly, 4))
+    out = []
+    for _ in range(2):
+        lat = Lattice(lx, ly, TAU, G, TB, TT, precision=precision, step=step, device=DEV)
+        lat.init_rt(P)
+        lat.step(100)
+        out.append((lat.get_pops(), lat.conservation()))
+        del lat
+    assert torch.equal(out[0][0], out[1][0]) and torch.equal(out[0][1], out[1][1])
