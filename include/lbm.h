@@ -156,7 +156,12 @@ lbm_status lbm_bc(lbm_ctx* ctx);
 /* BGK collision, eq. (1) with dt = 1, in place on the current buffer:
  * moments (eq. (2)), gravity shift, equilibrium, f <- f + (f^eq - f)/tau. */
 lbm_status lbm_collide(lbm_ctx* ctx);
-/* n >= 0 times (propagate, bc, collide), split or fused per step_kind. */
+/* n >= 0 times (propagate, bc, collide), split or fused per step_kind.
+ * It only launches kernels on the context's stream, so it can be captured
+ * into a HIP graph there (after at least one eager step).  A replay repeats
+ * the captured launches with the buffers they were captured with: capture an
+ * even n, which ends on the buffers it started from, and each replay then
+ * advances the state by n steps, bitwise as n eager steps would. */
 lbm_status lbm_step(lbm_ctx* ctx, int64_t n);
 
 /* ---- read-out and snapshots ---------------------------------------------- */
