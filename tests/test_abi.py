@@ -57,6 +57,11 @@ def test_host_side_validation():
     assert L.lbm_create(ctypes.byref(good), ctypes.c_void_p(4096 + 8), n, None, ctypes.byref(h)) == 1
     assert not h.value
     assert L.lbm_step_state(None, None, None) == 1
+    # every context call refuses a NULL context before touching the device
+    for name, args in (("lbm_step", (1,)), ("lbm_propagate", ()), ("lbm_collide", ()), ("lbm_sync", ()),
+                       ("lbm_adjoint_step", (None, None)), ("lbm_adjoint_take_dtau", (None,)),
+                       ("lbm_conservation", (None,))):
+        assert getattr(L, name)(None, *args) == 1, name
     # FP32 storage about halves the population buffers (on a lattice tall
     # enough for the ghost rows and padding not to dominate); the adjoint adds
     # FP64 lambda
