@@ -121,7 +121,9 @@ size_t lbm_workspace_bytes(const lbm_params* p);
 /* Bytes of one opaque state snapshot; 0 if *p is invalid. */
 size_t lbm_state_bytes(const lbm_params* p);
 
-/* Validates *p (lx, ly >= 7, tau > 0.5, known enums, reserved == 0) and binds
+/* Validates *p (lx, ly >= 7, lx * ly <= 2^31, tau > 0.5 and finite, finite
+ * g_y, known enums, adjoint 0, 1 or 2; else LBM_ERR_INVALID, and
+ * LBM_ERR_SIZE if bytes is too small) and binds
  * a context to dev_workspace (>= lbm_workspace_bytes(p) bytes, 256-byte
  * aligned, caller-owned, must outlive the context) and hip_stream (a
  * hipStream_t, or NULL for the default stream).  Zeroes the workspace.  The
