@@ -5,8 +5,9 @@
 // propagate's bandwidth can be quoted as a fraction of a plain copy measured
 // on the same GPU in the same run.  dst[i] = src[i] over `bytes` bytes in
 // 16-byte vectors, one workgroup per chunk of `block_bytes` bytes (1024, 2048
-// or 4096: 64, 128 or 256 threads), non-temporal loads and stores, hardware
-// block order (the fastest plain copy measured on MI355X used this form).
+// or 4096: 64, 128 or 256 threads), non-temporal loads and the library's
+// streaming stores (non-temporal, device scope: lbm::st_nt), hardware block
+// order (the fastest plain copy measured on MI355X used this form).
 //
 // int cp_copy(const void* src, void* dst, size_t bytes, int block_bytes,
 //             void* hip_stream)
@@ -112,8 +113,9 @@ typedef double v2 __attribute__((ext_vector_type(2)));
 template <int T>
 __global__ __launch_bounds__(T) void k_copy(const v2* __restrict__ src, v2* __restrict__ dst, size_t n)
 {
-    const size_t i = (size_t)blockIdx.x * T + threadIdx.x;
-    if (i < n) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+    const size_t b = (size_t)blockIdx.x * T;
+    if (b + threadIdx.x < n)
+        lbm::st_nt<v2>(dst + b, threadIdx.x * 16u, __builtin_nontemporal_load(src + b + threadIdx.x));
 }
 
 template <int T>

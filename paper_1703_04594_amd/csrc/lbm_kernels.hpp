@@ -148,10 +148,35 @@ __device__ __forceinline__ T ld_nt(const T* base, unsigned byte_off)
 {
     return __builtin_nontemporal_load(reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + byte_off));
 }
+// Streaming store of a 4-, 8- or 16-byte value at base + byte_off, base
+// block-uniform (it becomes a buffer resource in scalar registers).  The
+// store carries the non-temporal hint and device scope (cache policy nt sc1),
+// so it is written through the XCD's L2 without being kept there.  Against
+// plain non-temporal stores (same launches, bitwise-equal results, 2048x4096,
+// two runs each, ms) it took propagate from 0.772-0.778 to 0.766-0.767 (FP64)
+// and 0.389-0.390 to 0.382-0.383 (FP32), the in-place FP32 collide from 0.418
+// to 0.396, the reverse step with FP64 lambda from 1.082-1.083 to 1.066-1.068,
+// and the fused steps 0.3-0.5% lower; the fused FP64 step's access pattern
+// alone ran 0.831 -> 0.811.  Stores without nt, or with sc1 alone, were 5-8%
+// slower than nt.
+typedef unsigned u32x2_t __attribute__((ext_vector_type(2)));
+typedef unsigned u32x4_t __attribute__((ext_vector_type(4)));
+constexpr int STORE_CPOL_NT_SC1 = 2 | 16;
 template <typename T>
 __device__ __forceinline__ void st_nt(T* base, unsigned byte_off, T v)
 {
-    __builtin_nontemporal_store(v, reinterpret_cast<T*>(reinterpret_cast<char*>(base) + byte_off));
+    static_assert(sizeof(T) == 4 || sizeof(T) == 8 || sizeof(T) == 16, "4, 8 or 16-byte stores");
+    // raw buffer (stride 0) over the whole 32-bit offset range
+    const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(base, 0, -1, 0x00020000);
+    if constexpr (sizeof(T) == 4)
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)byte_off, 0,
+                                              STORE_CPOL_NT_SC1);
+    else if constexpr (sizeof(T) == 8)
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), r, (int)byte_off, 0,
+                                              STORE_CPOL_NT_SC1);
+    else
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4_t, v), r, (int)byte_off, 0,
+                                               STORE_CPOL_NT_SC1);
 }
 template <typename T>
 __device__ __forceinline__ void st_at(T* base, unsigned byte_off, T v)
@@ -221,7 +246,7 @@ __global__ __launch_bounds__(PROP_THREADS) void k_propagate(const S* __restrict_
 #pragma unroll
     for (int u = 0; u < UNROLL; ++u) {
         const int y = y0 + u * PROP_THREADS * VEC;
-        if (y < g.ly) __builtin_nontemporal_store((VA)v[u], reinterpret_cast<VA*>(dp + y));
+        if (y < g.ly) st_nt<VA>(reinterpret_cast<VA*>(dp), (unsigned)y * (unsigned)sizeof(S), (VA)v[u]);
     }
 }
 
@@ -366,14 +391,16 @@ inline FusedLaunch fused_fp64_launch(size_t nb256, int ncu, int max_lds)
     return {SITE_THREADS, 0u};
 }
 // The in-place collide of the split step takes the same kind of cap on large
-// lattices: 2 blocks per CU in FP32 (64 KB; 1-5% faster from 1024x2048 on, in
-// both layouts) and, in the columns layout, 1 block per CU in FP64 (96 KB;
-// 1.2-3% faster from 1024x1024 on).  In the planes layout the FP64 collide ran
-// 3% slower with 96 KB and unchanged with 64 KB, so it keeps full occupancy.
+// lattices: 2 blocks per CU (64 KB) in FP32 (1-5% faster from 1024x2048 on, in
+// both layouts) and, in the columns layout, in FP64 (with the streaming
+// stores above, 3-4% faster than 1 block per CU and 1-3% faster than full
+// occupancy from 1024x1024 to 4096x4096).  In the planes layout the FP64
+// collide ran 3% slower with 96 KB and unchanged with 64 KB, so it keeps full
+// occupancy.
 // Its blocks keep the XCD renumbering although a collide shares no lines
 // between blocks: in hardware order the FP64 columns collide ran 14-18%
 // slower at 2048x4096 and 4096x4096.
-constexpr unsigned COLLIDE_FP64_LDS_RESERVE = 96 * 1024;
+constexpr unsigned COLLIDE_FP64_LDS_RESERVE = 64 * 1024;
 constexpr unsigned COLLIDE_FP32_LDS_RESERVE = 64 * 1024;
 // The reverse step with FP64 lambda (256-thread blocks, 3 per CU by its
 // registers) takes a reserve that leaves 2 blocks per CU only when that does

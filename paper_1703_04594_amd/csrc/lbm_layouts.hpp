@@ -83,7 +83,9 @@ __global__ __launch_bounds__(ST_THREADS) void k_study_propagate(const double* __
     if (is < 0) { is += g.m; ks = ks == 0 ? g.vl - 1 : ks - 1; }
     else if (is >= g.m) { is -= g.m; ks = ks == g.vl - 1 ? 0 : ks + 1; }
     const double v = __builtin_nontemporal_load(src + st_index<LAY>(g, l, xs, ks, is));
-    __builtin_nontemporal_store(v, dst + st_index<LAY>(g, l, x, k, i));
+    // the destination is element j of segment seg (memory order), stored
+    // with the library's streaming store from the segment's start
+    st_nt(dst + (size_t)seg * seglen, j * 8u, v);
 }
 
 // collide in place, one site per thread.  Threads of a block take the sites
@@ -98,14 +100,16 @@ __global__ __launch_bounds__(SITE_THREADS) void k_study_collide(double* __restri
     const unsigned s = ch * SITE_THREADS + threadIdx.x;   // site of column x, in (i, k) order
     if (s >= (unsigned)g.ly) return;
     const int k = (int)(s & (unsigned)(g.vl - 1)), i = (int)(s >> g.lvl);
-    double* base = buf + st_index<LAY>(g, 0, (int)x, k, i);
+    double* col = buf + st_index<LAY>(g, 0, (int)x, 0, 0);
+    // the site's offset from its column's start, the same for every population
+    const size_t so = st_index<LAY>(g, 0, (int)x, k, i) - st_index<LAY>(g, 0, (int)x, 0, 0);
     const size_t stride = st_index<LAY>(g, 1, 0, 0, 0);    // distance between populations
     double f[NPOP];
 #pragma unroll
-    for (int l = 0; l < NPOP; ++l) f[l] = __builtin_nontemporal_load(base + l * stride);
+    for (int l = 0; l < NPOP; ++l) f[l] = __builtin_nontemporal_load(col + so + l * stride);
     collide_site<double, false>(f, args);
 #pragma unroll
-    for (int l = 0; l < NPOP; ++l) __builtin_nontemporal_store(f[l], base + l * stride);
+    for (int l = 0; l < NPOP; ++l) st_nt(col + l * stride, (unsigned)(so * 8), f[l]);
 }
 
 // canonical FP64 [37][lx][ly] <-> layout, one element per thread
