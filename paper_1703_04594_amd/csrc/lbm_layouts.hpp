@@ -108,8 +108,19 @@ __global__ __launch_bounds__(SITE_THREADS) void k_study_collide(double* __restri
 #pragma unroll
     for (int l = 0; l < NPOP; ++l) f[l] = __builtin_nontemporal_load(col + so + l * stride);
     collide_site<double, false>(f, args);
+    // A wave's stores of one population are one 512-byte run in SOA and CSOA,
+    // which take the library's streaming store.  In AOS they are 8-byte
+    // pieces 296 B apart, which that store writes through the L2 one at a
+    // time (AOS collide: 9.5 -> 31.5 ms at 2160x8192); AOS and CAOSOA (runs
+    // of VL elements 37 VL apart: -3% to +3% with it) keep plain
+    // non-temporal stores, which the L2 merges into whole lines.
+    if constexpr (st_per_population<LAY>()) {
 #pragma unroll
-    for (int l = 0; l < NPOP; ++l) st_nt(col + l * stride, (unsigned)(so * 8), f[l]);
+        for (int l = 0; l < NPOP; ++l) st_nt(col + l * stride, (unsigned)(so * 8), f[l]);
+    } else {
+#pragma unroll
+        for (int l = 0; l < NPOP; ++l) __builtin_nontemporal_store(f[l], col + so + l * stride);
+    }
 }
 
 // canonical FP64 [37][lx][ly] <-> layout, one element per thread
