@@ -158,7 +158,12 @@ __device__ __forceinline__ T ld_nt(const T* base, unsigned byte_off)
 // to 0.396, the reverse step with FP64 lambda from 1.082-1.083 to 1.066-1.068,
 // and the fused steps 0.3-0.5% lower; the fused FP64 step's access pattern
 // alone ran 0.831 -> 0.811.  Stores without nt, or with sc1 alone, were 5-8%
-// slower than nt.
+// slower than nt.  Below 2048x4096 device scope costs time instead (the
+// fused FP64 step 9% at 256x128, 2-4% at 512x512 and 1024x1024, 0.5-1.4% at
+// 1024x2048 and 2048x2048); choosing the scope per lattice with a uniform
+// flag before each store kept all 37 values live across the branches (FP32
+// step: 62 -> 126 VGPRs), so the stores keep the form that is faster on the
+// large lattices.
 typedef unsigned u32x2_t __attribute__((ext_vector_type(2)));
 typedef unsigned u32x4_t __attribute__((ext_vector_type(4)));
 constexpr int STORE_CPOL_NT_SC1 = 2 | 16;
