@@ -166,13 +166,20 @@ __device__ __forceinline__ T ld_nt(const T* base, unsigned byte_off)
 // large lattices.
 typedef unsigned u32x2_t __attribute__((ext_vector_type(2)));
 typedef unsigned u32x4_t __attribute__((ext_vector_type(4)));
-constexpr int STORE_CPOL_NT_SC1 = 2 | 16;
+// cache-policy bits of a gfx950 buffer instruction: nt (non-temporal) and
+// sc1 (scope bit 1: device scope)
+constexpr int CPOL_NT = 2, CPOL_SC1 = 16;
+constexpr int STORE_CPOL_NT_SC1 = CPOL_NT | CPOL_SC1;
+// Raw buffer descriptor (stride 0): num_records is a byte count, here the
+// whole 32-bit offset range; word 3 sets the 32-bit data format (field value 4
+// at bit 15), as raw accesses take their size from the instruction.
+constexpr int RAW_BUFFER_ALL_BYTES = -1;
+constexpr int RAW_BUFFER_WORD3 = 0x00020000;
 template <typename T>
 __device__ __forceinline__ void st_nt(T* base, unsigned byte_off, T v)
 {
     static_assert(sizeof(T) == 4 || sizeof(T) == 8 || sizeof(T) == 16, "4, 8 or 16-byte stores");
-    // raw buffer (stride 0) over the whole 32-bit offset range
-    const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(base, 0, -1, 0x00020000);
+    const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(base, 0, RAW_BUFFER_ALL_BYTES, RAW_BUFFER_WORD3);
     if constexpr (sizeof(T) == 4)
         __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)byte_off, 0,
                                               STORE_CPOL_NT_SC1);
