@@ -377,14 +377,14 @@ def run(args):
                      "propagate_fp64": round(bytes_fp64 / t_prop / 1e9 / HBM_PEAK_GBS, 3),
                      "collide_fp64": round(bytes_fp64 / t_coll / 1e9 / HBM_PEAK_GBS, 3)},
         "flop_frac": None if (lx, ly) != (2048, 4096) else {
-            "fused_fp64": flop_fraction("lbm::k_step_fused<double, true, true, true, 512>", t_fused),
+            "fused_fp64": flop_fraction("lbm::k_step_fused<double, true, true, true, 512, true>", t_fused),
             "collide_fp64": flop_fraction("lbm::k_collide<double, true, true>", t_coll),
-            "fused_fp32": flop_fraction("lbm::k_step_fused<float, true, true, true, 256>", t_fused32),
-            "adjoint_fp64_lambda": flop_fraction("lbm::k_adj_collide<float, double, true, true, 256>", t_adj["fp64"]),
-            "adjoint_fp32_lambda": flop_fraction("lbm::k_adj_collide<float, float, true, true, 64>", t_adj["fp32"])},
+            "fused_fp32": flop_fraction("lbm::k_step_fused<float, true, true, true, 256, true>", t_fused32),
+            "adjoint_fp64_lambda": flop_fraction("lbm::k_adj_collide<float, double, true, true, 256, true>", t_adj["fp64"]),
+            "adjoint_fp32_lambda": flop_fraction("lbm::k_adj_collide<float, float, true, true, 64, true>", t_adj["fp32"])},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic("lbm::k_step_fused<double, true, true, true, 512>") if (lx, ly) == (2048, 4096) else None,
+                     "traffic": measured_traffic("lbm::k_step_fused<double, true, true, true, 512, true>") if (lx, ly) == (2048, 4096) else None,
                      "kernel": "k_step_fused<double,wrap,walls>", "bytes_per_site": 592,
                      "algorithmic_bytes_per_launch": bytes_fp64},
     }

@@ -227,9 +227,11 @@ __device__ __forceinline__ void load_lambda(const L* __restrict__ buf, const Geo
 
 // One reverse step at site (x, y): lambda_{n+1} (load_lambda), the gather
 // g = bc(propagate(f_n)) of the snapshot f_n, collide^T, and mu stored at the
-// site (aligned, non-temporal); the block's d/dtau term goes to its slot of
+// site (aligned streaming stores); the block's d/dtau term goes to its slot of
 // partials (add: added to the slot, which then sums the terms of many steps).
-template <typename S, typename L, bool WALLS, bool GATHER, int T = adj_threads<L>()>
+// (DEV: the device-scope streaming stores, or the plain non-temporal ones
+// below DEV_STORES_MIN_BLOCKS_PER_CU blocks per CU)
+template <typename S, typename L, bool WALLS, bool GATHER, int T = adj_threads<L>(), bool DEV = true>
 __global__ __launch_bounds__(T) void k_adj_collide(
     const S* __restrict__ fn, Geo g, const L* __restrict__ lam_in, L* __restrict__ mu_out, Geo lg,
     AdjArgs a, const double* __restrict__ wall_rho, WallTable wt, double* __restrict__ partials, int add)
@@ -291,7 +293,7 @@ __global__ __launch_bounds__(T) void k_adj_collide(
         dtau = adjoint_site(m0, sx, sy, s2, Lg, lam, a);
         L* mcol = mu_out + lg.origin + (long long)x * lg.cs;
 #pragma unroll
-        for (int l = 0; l < NPOP; ++l) st_nt(mcol + (size_t)l * lg.ps, yd, (L)lam[l]);
+        for (int l = 0; l < NPOP; ++l) st_stream<DEV>(mcol + (size_t)l * lg.ps, yd, (L)lam[l]);
     }
     block_sum1<T>(dtau, partials, add != 0);
 }

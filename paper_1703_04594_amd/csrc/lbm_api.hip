@@ -111,6 +111,7 @@ struct lbm_ctx {
     unsigned fused_lds;  // dynamic LDS of the fused step's launch (occupancy cap; 0: none)
     int fused_threads;   // threads per block of the FP64 fused step (256 or 512)
     unsigned collide_lds;// the same for the split step's collide
+    bool dev_stores;     // fused and reverse steps with device-scope stores (dev_stores_for)
     unsigned adj_lds;    // the same for the reverse step
     std::string err;
 
@@ -286,8 +287,8 @@ lbm_status do_collide(lbm_ctx* c)
 
 // One fused step src -> dst (wall densities read from wr, written to wo),
 // T threads per block.
-template <typename S, bool WIDE, int T>
-void launch_fused_kernel(lbm_ctx* c, const S* src, S* dst, const double* wr, double* wo)
+template <typename S, bool WIDE, int T, bool DEV>
+void launch_fused_kernel_dev(lbm_ctx* c, const S* src, S* dst, const double* wr, double* wo)
 {
     const Geo& g = c->pl.geo;
     const bool walls = c->p.ybc == LBM_Y_WALLS;
@@ -295,13 +296,23 @@ void launch_fused_kernel(lbm_ctx* c, const S* src, S* dst, const double* wr, dou
     const unsigned lds = sizeof(S) == 8 ? c->fused_lds : 0u;
     const dim3 grid((unsigned)((g.ly + T - 1) / T) * (unsigned)g.lx);
     if (wrap && walls)
-        hipLaunchKernelGGL((k_step_fused<S, true, true, WIDE, T>), grid, dim3(T), lds, c->stream, src, dst, g, c->cargs, wr, c->wt, wo);
+        hipLaunchKernelGGL((k_step_fused<S, true, true, WIDE, T, DEV>), grid, dim3(T), lds, c->stream, src, dst, g,
+                           c->cargs, wr, c->wt, wo);
     else if (wrap)
-        hipLaunchKernelGGL((k_step_fused<S, true, false, WIDE, T>), grid, dim3(T), lds, c->stream, src, dst, g, c->cargs, wr, c->wt, wo);
+        hipLaunchKernelGGL((k_step_fused<S, true, false, WIDE, T, DEV>), grid, dim3(T), lds, c->stream, src, dst, g,
+                           c->cargs, wr, c->wt, wo);
     else if (walls)
-        hipLaunchKernelGGL((k_step_fused<S, false, true, WIDE, T>), grid, dim3(T), lds, c->stream, src, dst, g, c->cargs, wr, c->wt, wo);
+        hipLaunchKernelGGL((k_step_fused<S, false, true, WIDE, T, DEV>), grid, dim3(T), lds, c->stream, src, dst, g,
+                           c->cargs, wr, c->wt, wo);
     else
-        hipLaunchKernelGGL((k_step_fused<S, false, false, WIDE, T>), grid, dim3(T), lds, c->stream, src, dst, g, c->cargs, wr, c->wt, wo);
+        hipLaunchKernelGGL((k_step_fused<S, false, false, WIDE, T, DEV>), grid, dim3(T), lds, c->stream, src, dst, g,
+                           c->cargs, wr, c->wt, wo);
+}
+template <typename S, bool WIDE, int T>
+void launch_fused_kernel(lbm_ctx* c, const S* src, S* dst, const double* wr, double* wo)
+{
+    if (c->dev_stores) launch_fused_kernel_dev<S, WIDE, T, true>(c, src, dst, wr, wo);
+    else launch_fused_kernel_dev<S, WIDE, T, false>(c, src, dst, wr, wo);
 }
 
 template <typename S>
@@ -532,21 +543,23 @@ namespace {
 // Blocks of the reverse step's kernel that fit one CU at full occupancy
 // (0 if the runtime cannot tell).
 template <typename S, typename L>
-int adj_blocks_per_cu_t()
+int adj_blocks_per_cu_t(bool dev_stores)
 {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_adj_collide<S, L, true, true>, adj_threads<L>(), 0) !=
-        hipSuccess)
-        return 0;
-    return n;
+    constexpr int T = adj_threads<L>();
+    const hipError_t e =
+        dev_stores ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_adj_collide<S, L, true, true, T, true>, T, 0)
+                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_adj_collide<S, L, true, true, T, false>, T, 0);
+    return e == hipSuccess ? n : 0;
 }
 
-int adj_blocks_per_cu(const lbm_params* p)
+// blocks per CU of the reverse step this context launches
+int adj_blocks_per_cu(const lbm_params* p, bool dev_stores)
 {
     const bool lam32 = p->adjoint == 2;
     if (p->precision == LBM_FP64)
-        return lam32 ? adj_blocks_per_cu_t<double, float>() : adj_blocks_per_cu_t<double, double>();
-    return lam32 ? adj_blocks_per_cu_t<float, float>() : adj_blocks_per_cu_t<float, double>();
+        return lam32 ? adj_blocks_per_cu_t<double, float>(dev_stores) : adj_blocks_per_cu_t<double, double>(dev_stores);
+    return lam32 ? adj_blocks_per_cu_t<float, float>(dev_stores) : adj_blocks_per_cu_t<float, double>(dev_stores);
 }
 
 }  // namespace
@@ -592,6 +605,7 @@ lbm_status lbm_create(const lbm_params* p, void* dev_workspace, size_t bytes, vo
     c->fused_lds = 0;
     c->fused_threads = SITE_THREADS;
     c->collide_lds = 0;
+    c->dev_stores = false;
     int dev = 0, ncu = 0, max_lds = 0;
     if (hipGetDevice(&dev) == hipSuccess &&
         hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
@@ -599,6 +613,7 @@ lbm_status lbm_create(const lbm_params* p, void* dev_workspace, size_t bytes, vo
         const FusedLaunch fl = fused_fp64_launch(site_grid(pl.geo).x, ncu, max_lds);
         c->fused_threads = fl.threads;
         c->fused_lds = fl.lds;
+        c->dev_stores = dev_stores_for(site_grid(pl.geo).x, ncu);
         if ((size_t)site_grid(pl.geo).x >= (size_t)FUSED_FP64_CAP_MIN_BLOCKS_PER_CU * (size_t)ncu) {
             const unsigned coll = p->precision == LBM_FP64 ? COLLIDE_FP64_LDS_RESERVE : COLLIDE_FP32_LDS_RESERVE;
             if ((size_t)max_lds >= coll && (p->precision != LBM_FP64 || p->layout == LBM_LAYOUT_COLUMNS))
@@ -608,7 +623,7 @@ lbm_status lbm_create(const lbm_params* p, void* dev_workspace, size_t bytes, vo
     c->adj_lds = 0;
     // (256-thread reverse steps only: FP64 lambda)
     if (p->adjoint == 1 && ncu > 0 && (size_t)max_lds >= ADJ_LDS_RESERVE) {
-        const int full = adj_blocks_per_cu(p);
+        const int full = adj_blocks_per_cu(p, c->dev_stores);
         const size_t nb = site_grid(pl.geo).x;
         auto rounds = [&](int per_cu) { return (nb + (size_t)per_cu * ncu - 1) / ((size_t)per_cu * ncu); };
         if (full > ADJ_CAP_BLOCKS_PER_CU && rounds(ADJ_CAP_BLOCKS_PER_CU) <= rounds(full))

@@ -158,12 +158,11 @@ __device__ __forceinline__ T ld_nt(const T* base, unsigned byte_off)
 // to 0.396, the reverse step with FP64 lambda from 1.082-1.083 to 1.066-1.068,
 // and the fused steps 0.3-0.5% lower; the fused FP64 step's access pattern
 // alone ran 0.831 -> 0.811.  Stores without nt, or with sc1 alone, were 5-8%
-// slower than nt.  Below 2048x4096 device scope costs time instead (the
-// fused FP64 step 9% at 256x128, 2-4% at 512x512 and 1024x1024, 0.5-1.4% at
-// 1024x2048 and 2048x2048); choosing the scope per lattice with a uniform
-// flag before each store kept all 37 values live across the branches (FP32
-// step: 62 -> 126 VGPRs), so the stores keep the form that is faster on the
-// large lattices.
+// slower than nt.  Below 2048x4096 device scope costs the fused and reverse
+// steps time instead, so those take the store form as a template parameter
+// (st_stream), chosen per lattice at launch; a uniform flag tested before
+// each store instead kept all 37 values live across the branches (FP32
+// step: 62 -> 126 VGPRs).
 typedef unsigned u32x2_t __attribute__((ext_vector_type(2)));
 typedef unsigned u32x4_t __attribute__((ext_vector_type(4)));
 // cache-policy bits of a gfx950 buffer instruction: nt (non-temporal) and
@@ -189,6 +188,29 @@ __device__ __forceinline__ void st_nt(T* base, unsigned byte_off, T v)
     else
         __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4_t, v), r, (int)byte_off, 0,
                                                STORE_CPOL_NT_SC1);
+}
+// The fused step's and reverse step's stores: the device-scope streaming
+// store above (DEV), or the plain non-temporal store, which their
+// instantiations for lattices below DEV_STORES_MIN_BLOCKS_PER_CU blocks per CU
+// use.
+template <bool DEV, typename T>
+__device__ __forceinline__ void st_stream(T* base, unsigned byte_off, T v)
+{
+    if constexpr (DEV) st_nt(base, byte_off, v);
+    else __builtin_nontemporal_store(v, reinterpret_cast<T*>(reinterpret_cast<char*>(base) + byte_off));
+}
+// Device scope pays on large lattices only (see st_nt): the fused and reverse
+// steps take it from this many site blocks (of SITE_THREADS) per CU on,
+// i.e. from 8,388,608 sites (2048x4096) on a 256-CU GPU.  A/B of the two
+// store forms on one box (fused FP64 step / reverse step with FP64 lambda,
+// us per step, two runs each): 256x128 8.4 / 12.6 with plain non-temporal
+// stores against 9.2 / 13.5 at device scope, 512x512 28.2 / 44.0 against
+// 28.8-29.3 / 44.9, 1024x1024 119 / 183 against 123 / 186, 2048x2048 440 /
+// 559 against 446 / 557, 2048x4096 835-837 / 1082 against 833-834 / 1067.
+constexpr unsigned DEV_STORES_MIN_BLOCKS_PER_CU = 128;
+inline bool dev_stores_for(size_t nb256, int ncu)
+{
+    return ncu > 0 && nb256 >= (size_t)DEV_STORES_MIN_BLOCKS_PER_CU * (size_t)ncu;
 }
 template <typename T>
 __device__ __forceinline__ void st_at(T* base, unsigned byte_off, T v)
@@ -423,10 +445,12 @@ constexpr unsigned COLLIDE_FP32_LDS_RESERVE = 64 * 1024;
 // 64-thread blocks and no cap.
 constexpr unsigned ADJ_LDS_RESERVE = 64 * 1024;
 constexpr int ADJ_CAP_BLOCKS_PER_CU = 2;
-template <typename S, bool WRAP, bool WALLS, bool WIDE = true, int T = SITE_THREADS>
+// DEV: the device-scope streaming stores (large lattices) or the plain
+// non-temporal ones (below DEV_STORES_MIN_BLOCKS_PER_CU blocks per CU)
+template <typename S, bool WRAP, bool WALLS, bool WIDE = true, int T = SITE_THREADS, bool DEV = true>
 __global__ __launch_bounds__(T) void k_step_fused(const S* __restrict__ src, S* __restrict__ dst, Geo g,
-                                                          CollideArgs args, const double* __restrict__ wall_rho, WallTable wt,
-                                                          double* __restrict__ wall_rho_out)
+                                                  CollideArgs args, const double* __restrict__ wall_rho, WallTable wt,
+                                                  double* __restrict__ wall_rho_out)
 {
     using Cc = typename Store<S>::C;
     const SiteBlock sb = site_block<sizeof(S) == 8, T>(g);
@@ -466,7 +490,7 @@ __global__ __launch_bounds__(T) void k_step_fused(const S* __restrict__ src, S* 
     collide_site<Cc, Store<S>::shifted, WIDE>(f, args);
     S* col = dst + g.origin + (long long)x * g.cs;
 #pragma unroll
-    for (int l = 0; l < NPOP; ++l) st_nt(col + (size_t)l * g.ps, yb, (S)f[l]);
+    for (int l = 0; l < NPOP; ++l) st_stream<DEV>(col + (size_t)l * g.ps, yb, (S)f[l]);
     if (WALLS) store_wall_density<S>(f, g, x, y, wall_rho_out);
 }
 
